@@ -1,0 +1,450 @@
+/* CPU oracle for the IMM hot path -- TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Plain C, deliberately simple.  Each function names the passage of the gIM paper (or of
+ * the IMM / Philox papers) that it follows.  Build: gcc -O2 -fopenmp -ffp-contract=off.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon et al., SC'11, Sec. 5: the Philox round with multipliers
+ * 0xD2511F53 / 0xCD9E8D57 and Weyl key increments 0x9E3779B9 / 0xBB67AE85).
+ * One round maps (c0,c1,c2,c3) to (hi(M1*c2)^c1^k0, lo(M1*c2), hi(M0*c0)^c3^k1, lo(M0*c0));
+ * the key is bumped between rounds.
+ * ---------------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static uint32_t draw_word(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                          int word) {
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[word];
+}
+
+/* ------------------------------------------------------------------------------------
+ * Threshold encodings.
+ * IC (Sec. II-B; Alg. 3's test "p < p_uv"): an edge with probability p is live when a
+ * uniform 32-bit draw x satisfies x < floor(p * 2^32); p = 1 saturates to "always".
+ * ---------------------------------------------------------------------------------- */
+uint32_t orc_ic_threshold(float p) {
+    double t = floor((double)p * 4294967296.0);
+    if (t >= 4294967296.0) return ORC_ALWAYS;
+    return (uint32_t)t;
+}
+
+int orc_encode_ic(int64_t m, const float* p, uint32_t* thr) {
+    for (int64_t e = 0; e < m; ++e) {
+        if (!(p[e] >= 0.0f && p[e] <= 1.0f)) return -1;
+        thr[e] = orc_ic_threshold(p[e]);
+    }
+    return 0;
+}
+
+/* LT (Sec. II-B Eq. 1 and Sec. III-G): a vertex picks at most one in-edge, edge j with
+ * probability w_j / sum(w); a uniform draw is compared with consecutive prefix sums of the
+ * in-weights and the first prefix above the draw wins.  Prefix sums are scaled to 2^32 in
+ * exact integer arithmetic; the last one saturates so that the weights sum to one. */
+int orc_encode_lt(int32_t n, const int64_t* in_off, const uint32_t* w, uint32_t* cum) {
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t s = in_off[v], e = in_off[v + 1];
+        if (e < s) return -1;
+        uint64_t total = 0;
+        for (int64_t j = s; j < e; ++j) {
+            uint64_t wj = w ? (uint64_t)w[j] : 1u;
+            if (wj == 0) return -2;
+            total += wj;
+        }
+        uint64_t prefix = 0;
+        for (int64_t j = s; j < e; ++j) {
+            prefix += w ? (uint64_t)w[j] : 1u;
+            if (j == e - 1) {
+                cum[j] = ORC_ALWAYS;
+            } else {
+                unsigned __int128 num = (unsigned __int128)prefix << 32;
+                cum[j] = (uint32_t)(num / total);
+            }
+        }
+    }
+    return 0;
+}
+
+/* randSelect(V) of Alg. 3: a uniform root by multiply-shift of one 32-bit draw. */
+int32_t orc_root(uint64_t seed, uint32_t r, int32_t n) {
+    uint32_t w0 = draw_word(seed, r, 0u, 0u, ORC_DOMAIN_ROOT, 0);
+    return (int32_t)(((uint64_t)w0 * (uint64_t)(uint32_t)n) >> 32);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Random RR set under IC (Sec. II-E definition; Alg. 3; Sec. III-A "Parallel BFS").
+ * The RR set of root v in a live-edge instance g is every vertex that reaches v in g.
+ * A BFS from v over in-edges, testing each in-edge once with its own draw, enumerates
+ * exactly that set.  The root is marked visited before the search starts so that it is
+ * never enqueued twice.
+ * ---------------------------------------------------------------------------------- */
+int64_t orc_rr_ic(int32_t n, const int64_t* in_off, const int32_t* in_src,
+                  const uint32_t* thr, uint64_t seed, uint32_t r, int32_t* out,
+                  uint8_t* mark, int64_t* edges) {
+    int64_t size = 0, head = 0, examined = 0;
+    int32_t root = orc_root(seed, r, n);
+    out[size++] = root;
+    mark[root] = 1;
+    while (head < size) {
+        int32_t u = out[head++];
+        for (int64_t e = in_off[u]; e < in_off[u + 1]; ++e) {
+            ++examined;
+            uint32_t x = draw_word(seed, r, (uint32_t)(e >> 2), 0u, ORC_DOMAIN_IC, (int)(e & 3));
+            int live = (thr[e] == ORC_ALWAYS) || (x < thr[e]);
+            int32_t w = in_src[e];
+            if (live && !mark[w]) {
+                mark[w] = 1;
+                out[size++] = w;
+            }
+        }
+    }
+    for (int64_t i = 0; i < size; ++i) mark[out[i]] = 0;
+    if (edges) *edges = examined;
+    return size;
+}
+
+/* Random RR set under LT (Sec. III-A: at most one live in-edge per vertex; Sec. III-G).
+ * From the current vertex, one draw selects the first in-edge whose cumulative threshold
+ * exceeds it; the walk continues from that in-neighbour and stops when the vertex has no
+ * in-edge, no edge is selected, or the selected in-neighbour is already in the set. */
+int64_t orc_rr_lt(int32_t n, const int64_t* in_off, const int32_t* in_src,
+                  const uint32_t* cum, uint64_t seed, uint32_t r, int32_t* out,
+                  uint8_t* mark, int64_t* edges) {
+    int64_t size = 0, examined = 0;
+    int32_t v = orc_root(seed, r, n);
+    out[size++] = v;
+    mark[v] = 1;
+    for (;;) {
+        int64_t s = in_off[v], e = in_off[v + 1];
+        if (e == s) break;
+        examined += e - s;
+        uint32_t x = draw_word(seed, r, (uint32_t)v, 0u, ORC_DOMAIN_LT, 0);
+        int64_t pick = -1;
+        for (int64_t j = s; j < e; ++j) {
+            if (cum[j] == ORC_ALWAYS || x < cum[j]) {
+                pick = j;
+                break;
+            }
+        }
+        if (pick < 0) break;
+        int32_t u = in_src[pick];
+        if (mark[u]) break;
+        mark[u] = 1;
+        out[size++] = u;
+        v = u;
+    }
+    for (int64_t i = 0; i < size; ++i) mark[out[i]] = 0;
+    if (edges) *edges = examined;
+    return size;
+}
+
+/* ------------------------------------------------------------------------------------
+ * RR-set collection R (Alg. 1 step 1; Alg. 6 concatenates sets into one array RR with
+ * offsets).  Sets are kept in index order and each set sorted ascending.
+ * ---------------------------------------------------------------------------------- */
+struct orc_pool {
+    int32_t n;
+    int64_t m;
+    const int64_t* in_off;
+    const int32_t* in_src;
+    const uint32_t* thr;
+    int model;
+    uint64_t seed;
+    int64_t count, cap_sets;
+    int64_t* off;       /* count + 1 */
+    int64_t* edges;     /* per set */
+    int32_t* ids;
+    int64_t cap_ids;
+};
+
+orc_pool* orc_pool_new(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                       const uint32_t* thr_or_cum, int model, uint64_t seed) {
+    if (n < 1 || m < 0 || (model != 0 && model != 1)) return NULL;
+    orc_pool* p = (orc_pool*)calloc(1, sizeof(orc_pool));
+    p->n = n; p->m = m; p->in_off = in_off; p->in_src = in_src; p->thr = thr_or_cum;
+    p->model = model; p->seed = seed;
+    p->cap_sets = 1024;
+    p->off = (int64_t*)calloc((size_t)p->cap_sets + 1, sizeof(int64_t));
+    p->edges = (int64_t*)calloc((size_t)p->cap_sets, sizeof(int64_t));
+    p->cap_ids = 1 << 16;
+    p->ids = (int32_t*)malloc((size_t)p->cap_ids * sizeof(int32_t));
+    return p;
+}
+
+void orc_pool_free(orc_pool* p) {
+    if (!p) return;
+    free(p->off); free(p->edges); free(p->ids); free(p);
+}
+
+static int cmp_i32(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+int orc_pool_extend(orc_pool* p, int64_t upto, int nthreads) {
+    if (upto <= p->count) return 0;
+    if (upto > 0xFFFFFFFFll) return -1;     /* set index must fit the 32-bit counter word */
+    if (upto > p->cap_sets) {
+        int64_t cap = p->cap_sets;
+        while (cap < upto) cap *= 2;
+        p->off = (int64_t*)realloc(p->off, (size_t)(cap + 1) * sizeof(int64_t));
+        p->edges = (int64_t*)realloc(p->edges, (size_t)cap * sizeof(int64_t));
+        p->cap_sets = cap;
+    }
+    if (nthreads < 1) nthreads = 1;
+    const int64_t chunk = 1 << 15;
+    int32_t** sets = (int32_t**)malloc(sizeof(int32_t*) * (size_t)chunk);
+    int64_t* sizes = (int64_t*)malloc(sizeof(int64_t) * (size_t)chunk);
+    for (int64_t base = p->count; base < upto; base += chunk) {
+        int64_t cnt = upto - base < chunk ? upto - base : chunk;
+        #pragma omp parallel num_threads(nthreads)
+        {
+            int32_t* out = (int32_t*)malloc(sizeof(int32_t) * (size_t)p->n);
+            uint8_t* mark = (uint8_t*)calloc((size_t)p->n, 1);
+            #pragma omp for schedule(dynamic, 64)
+            for (int64_t j = 0; j < cnt; ++j) {
+                int64_t ex = 0, sz;
+                uint32_t r = (uint32_t)(base + j);
+                if (p->model == 0)
+                    sz = orc_rr_ic(p->n, p->in_off, p->in_src, p->thr, p->seed, r, out, mark, &ex);
+                else
+                    sz = orc_rr_lt(p->n, p->in_off, p->in_src, p->thr, p->seed, r, out, mark, &ex);
+                qsort(out, (size_t)sz, sizeof(int32_t), cmp_i32);
+                sets[j] = (int32_t*)malloc(sizeof(int32_t) * (size_t)sz);
+                memcpy(sets[j], out, sizeof(int32_t) * (size_t)sz);
+                sizes[j] = sz;
+                p->edges[base + j] = ex;
+            }
+            free(out);
+            free(mark);
+        }
+        for (int64_t j = 0; j < cnt; ++j) {
+            int64_t at = p->off[base + j];
+            if (at + sizes[j] > p->cap_ids) {
+                int64_t cap = p->cap_ids;
+                while (cap < at + sizes[j]) cap *= 2;
+                p->ids = (int32_t*)realloc(p->ids, (size_t)cap * sizeof(int32_t));
+                p->cap_ids = cap;
+            }
+            memcpy(p->ids + at, sets[j], sizeof(int32_t) * (size_t)sizes[j]);
+            p->off[base + j + 1] = at + sizes[j];
+            free(sets[j]);
+        }
+        p->count = base + cnt;
+    }
+    free(sets);
+    free(sizes);
+    return 0;
+}
+
+int64_t orc_pool_count(const orc_pool* p) { return p->count; }
+
+int64_t orc_pool_total(const orc_pool* p, int64_t first, int64_t count) {
+    if (first < 0 || count < 0 || first + count > p->count) return -1;
+    return p->off[first + count] - p->off[first];
+}
+
+int64_t orc_pool_edges(const orc_pool* p, int64_t first, int64_t count) {
+    if (first < 0 || count < 0 || first + count > p->count) return -1;
+    int64_t s = 0;
+    for (int64_t r = first; r < first + count; ++r) s += p->edges[r];
+    return s;
+}
+
+int orc_pool_export(const orc_pool* p, int64_t first, int64_t count, int64_t* off,
+                    int32_t* ids) {
+    if (first < 0 || count < 0 || first + count > p->count) return -1;
+    int64_t base = p->off[first];
+    for (int64_t i = 0; i <= count; ++i) off[i] = p->off[first + i] - base;
+    if (ids) memcpy(ids, p->ids + base, sizeof(int32_t) * (size_t)(p->off[first + count] - base));
+    return 0;
+}
+
+/* Occur[] of Sec. III-B: how many sets of the range contain each vertex. */
+int orc_pool_hist(const orc_pool* p, int64_t first, int64_t count, uint32_t* hist) {
+    if (first < 0 || count < 0 || first + count > p->count) return -1;
+    memset(hist, 0, sizeof(uint32_t) * (size_t)p->n);
+    for (int64_t i = p->off[first]; i < p->off[first + count]; ++i) hist[p->ids[i]]++;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Greedy maximum coverage (Alg. 1 lines 6-10; counters as Occur of Sec. III-H, covered
+ * flags as in Alg. 7).  Round i takes the vertex outside S that lies in the most sets not
+ * yet covered -- the smallest id among equals -- then removes every set containing it.
+ * ---------------------------------------------------------------------------------- */
+int orc_greedy_sets(int32_t n, int64_t nsets, const int64_t* off, const int32_t* ids,
+                    int32_t k, int32_t* seeds, int64_t* covered) {
+    if (k < 0 || k > n) return -1;
+    int64_t* cnt = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+    uint8_t* chosen = (uint8_t*)calloc((size_t)n, 1);
+    uint8_t* done = (uint8_t*)calloc((size_t)(nsets > 0 ? nsets : 1), 1);
+    for (int64_t i = off[0]; i < off[nsets]; ++i) cnt[ids[i]]++;
+    int64_t ncov = 0;
+    for (int32_t round = 0; round < k; ++round) {
+        int32_t best = -1;
+        for (int32_t v = 0; v < n; ++v) {
+            if (chosen[v]) continue;
+            if (best < 0 || cnt[v] > cnt[best]) best = v;
+        }
+        chosen[best] = 1;
+        seeds[round] = best;
+        for (int64_t r = 0; r < nsets; ++r) {
+            if (done[r]) continue;
+            int hit = 0;
+            for (int64_t i = off[r]; i < off[r + 1]; ++i)
+                if (ids[i] == best) { hit = 1; break; }
+            if (!hit) continue;
+            done[r] = 1;
+            ++ncov;
+            for (int64_t i = off[r]; i < off[r + 1]; ++i) cnt[ids[i]]--;
+        }
+    }
+    free(cnt); free(chosen); free(done);
+    if (covered) *covered = ncov;
+    return 0;
+}
+
+int orc_pool_greedy(const orc_pool* p, int64_t first, int64_t count, int32_t k,
+                    int32_t* seeds, int64_t* covered) {
+    if (first < 0 || count < 0 || first + count > p->count) return -1;
+    return orc_greedy_sets(p->n, count, p->off + first, p->ids, k, seeds, covered);
+}
+
+/* ------------------------------------------------------------------------------------
+ * IMM sample sizes (Tang et al. 2015; the paper defers f(n, eps, k) of Alg. 2 and the
+ * final theta = lambda* / LB to that work).  Natural logarithms throughout except log2 n
+ * in the loop bound and in ln(log2 n).  ln C(n,k) is the ascending sum of
+ * ln(n-i) - ln(i+1), so that it is reproducible without lgamma.
+ * ---------------------------------------------------------------------------------- */
+static double ln_of(double x) {
+    volatile double v = x;      /* keep every logarithm a run-time libm call */
+    return log(v);
+}
+
+static const double ORC_E = 2.718281828459045;
+
+double orc_log_binom(int64_t n, int64_t k) {
+    double s = 0.0;
+    for (int64_t i = 0; i < k; ++i) s += ln_of((double)(n - i)) - ln_of((double)(i + 1));
+    return s;
+}
+
+double orc_ell_adjusted(int64_t n, double ell) {
+    return ell * (1.0 + ln_of(2.0) / ln_of((double)n));
+}
+
+double orc_lambda_prime(int64_t n, int64_t k, double eps, double ell_adj) {
+    double ep = sqrt(2.0) * eps;
+    double lnC = orc_log_binom(n, k);
+    volatile double l2 = log2((double)n);
+    return (2.0 + 2.0 / 3.0 * ep) * (lnC + ell_adj * ln_of((double)n) + ln_of(l2)) *
+           (double)n / (ep * ep);
+}
+
+double orc_lambda_star(int64_t n, int64_t k, double eps, double ell_adj) {
+    double lnC = orc_log_binom(n, k);
+    double a = sqrt(ell_adj * ln_of((double)n) + ln_of(2.0));
+    double b = sqrt((1.0 - 1.0 / ORC_E) * (lnC + ell_adj * ln_of((double)n) + ln_of(2.0)));
+    return 2.0 * (double)n * ((1.0 - 1.0 / ORC_E) * a + b) * ((1.0 - 1.0 / ORC_E) * a + b) /
+           (eps * eps);
+}
+
+/* Loop bound of Alg. 2, log2(n) - 1, read as floor(log2 n) - 1. */
+int32_t orc_imax(int64_t n) {
+    int32_t bits = 0;
+    while (((int64_t)1 << bits) <= n) ++bits;   /* bit length of n */
+    return bits - 2;
+}
+
+/* Alg. 2 (LB estimation) followed by Alg. 1 (sample theta = lambda* / LB sets, then greedy).
+ * Sets generated during estimation are reused for the final sample unless fresh_final is
+ * set, in which case the final sets are indices [|R_est|, |R_est| + theta). */
+int orc_imm_solve(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                  const float* ic_p, const uint32_t* lt_w, int model, uint64_t seed,
+                  int32_t k, double eps, double ell, int fresh_final, int nthreads,
+                  int32_t* seeds, int64_t* info_i, double* info_d) {
+    if (n < 2 || m < 0 || k < 1 || k > n || !(eps > 0.0 && eps < 1.0) || !(ell > 0.0))
+        return -1;
+    uint32_t* thr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(m > 0 ? m : 1));
+    int rc = (model == 0) ? (ic_p ? orc_encode_ic(m, ic_p, thr) : -1)
+                          : orc_encode_lt(n, in_off, lt_w, thr);
+    if (rc != 0) { free(thr); return -2; }
+    orc_pool* pool = orc_pool_new(n, m, in_off, in_src, thr, model, seed);
+
+    double L = orc_ell_adjusted(n, ell);
+    double ep = sqrt(2.0) * eps;
+    double lamP = orc_lambda_prime(n, k, eps, L);
+    double lamS = orc_lambda_star(n, k, eps, L);
+    int32_t imax = orc_imax(n);
+    double LB = 1.0;
+    int64_t cov = 0, phases = 0;
+    for (int32_t i = 1; i <= imax; ++i) {
+        double x = (double)n / (double)((int64_t)1 << i);
+        int64_t th = (int64_t)ceil(lamP / x);
+        if (orc_pool_extend(pool, th > pool->count ? th : pool->count, nthreads) != 0) {
+            rc = -3; goto out;
+        }
+        int64_t R = pool->count;
+        orc_pool_greedy(pool, 0, R, k, seeds, &cov);
+        ++phases;
+        if ((double)n * (double)cov / (double)R >= (1.0 + ep) * x) {
+            LB = (double)n * (double)cov / (double)R / (1.0 + ep);
+            break;
+        }
+    }
+    {
+        int64_t theta = (int64_t)ceil(lamS / LB);
+        int64_t first = fresh_final ? pool->count : 0;
+        int64_t upto = fresh_final ? pool->count + theta
+                                   : (theta > pool->count ? theta : pool->count);
+        if (orc_pool_extend(pool, upto, nthreads) != 0) { rc = -3; goto out; }
+        int64_t R = upto - first;
+        orc_pool_greedy(pool, first, R, k, seeds, &cov);
+        ++phases;
+        info_i[0] = theta;
+        info_i[1] = pool->count;
+        info_i[2] = cov;
+        info_i[3] = phases;
+        info_i[4] = orc_pool_edges(pool, 0, pool->count);
+        info_i[5] = orc_pool_total(pool, 0, pool->count);
+        info_d[0] = LB;
+        info_d[1] = (double)n * (double)cov / (double)R;
+        info_d[2] = lamP;
+        info_d[3] = lamS;
+    }
+out:
+    orc_pool_free(pool);
+    free(thr);
+    return rc;
+}
