@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the IMM hot path on one MI355X.
+
+One step = one full IMM solve (gIM Alg. 2 LB estimation + Alg. 1 final sample and greedy
+max coverage) on a graph already resident in HBM: R-MAT scale 20 (2^20 vertices, 2^24
+edges), weighted-cascade IC probabilities, k = 50, eps = 0.1, ell = 1.
+
+Prints ONE JSON line: the metric is RR sets generated per second over the whole solve
+(value), with edges examined per second, seconds per query, the roofline of the dominant
+kernel (RR generation, bound by integer ALU work: Philox4x32-10 evaluations) measured
+from HIP events around its launches, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RR sets/s and GTEPS (HBM GB/s vs peak); IMM s/query and p99 batched vs plain"
+
+# Integer-ALU peak of MI355X for Philox4x32-10 (derivation in the design doc): 256 CUs x 64
+# VALU lanes x 2.4 GHz = 39.32e12 lane-cycles/s; one Philox4x32-10 costs 100 lane-cycles
+# (10 rounds x [2 quarter-rate 32x32->64 multiplies = 8, 2 three-input XORs = 2]).
+ALU_LANE_CYCLES = 256 * 64 * 2.4e9
+PHILOX_LANE_CYCLES = 100.0
+PEAK_GPHILOX = ALU_LANE_CYCLES / PHILOX_LANE_CYCLES / 1e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), cpu=model, host=platform.node())
+
+
+def workload(name: str):
+    from synth import configs
+    if name == "c1":
+        return configs.c1()
+    if name == "c2":
+        return configs.c2()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(w) -> dict:
+    g = w.graph
+    return {"workload": f"{w.name}: {g.meta.get('kind')} n={g.n} m={g.m}, {w.model}, "
+                        f"k={w.k}, eps={w.eps}, ell={w.ell}",
+            "n": g.n, "m": g.m, "model": w.model, "k": w.k, "eps": w.eps, "ell": w.ell,
+            "pool_seed": hex(w.seed)}
+
+
+def traffic_from_profile(kernel: str, workload_name: str):
+    """HBM bytes per launch from the committed counter summary, if it matches the current
+    kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_name}.json")
+    src = os.path.join(ROOT, "paper_2009_07325_amd", "csrc", "rr_gen.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec.get("kernel_src_sha256") != sha:
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(w, seconds: float) -> dict:
+    """The oracle (as it stands) on a bounded sample of the same workload: RR sets
+    [0, S) generated in chunks until `seconds` of generation, then greedy selection of
+    k seeds over them; throughput = S / (generation + selection time)."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    pool = oracle.Pool(w.graph, oracle.IC if w.model == "IC" else oracle.LT, w.seed,
+                       ic_p=w.ic_p, lt_w=w.lt_w)
+    t0 = time.perf_counter()
+    count, chunk = 0, 2000
+    while time.perf_counter() - t0 < seconds:
+        count += chunk
+        pool.extend(count, threads=threads)
+        chunk = min(chunk * 2, 50_000)
+    t_gen = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    pool.greedy(w.k, 0, count)
+    t_sel = time.perf_counter() - t1
+    return {"value": count / (t_gen + t_sel), "unit": "RR sets/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"RR sets [0, {count}) of the same pool (generation {t_gen:.1f} s) + "
+                      f"greedy k={w.k} over them ({t_sel:.1f} s), {threads} threads"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X: this build has no multi-GPU path "
+              "(RR index ranges would shard across GPUs; see DESIGN.md). Use --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import paper_2009_07325_amd as imm
+    log("host:", json.dumps(host_info()))
+    t = time.perf_counter()
+    w = workload(args.workload)
+    log(f"workload {w.name}: n={w.graph.n} m={w.graph.m} built in {time.perf_counter() - t:.1f}s")
+    imm.imm_init(0)
+    model = imm.IMM_IC if w.model == "IC" else imm.IMM_LT
+    g = imm.Graph.from_arrays(w.graph.n, w.graph.in_off, w.graph.in_src, ic_p=w.ic_p,
+                              lt_w=w.lt_w, lt=(w.model == "LT"))
+
+    def step():
+        return imm.imm_solve(g.handle, w.k, w.eps, w.ell, model, w.seed)
+
+    for i in range(args.warmup):
+        seeds, info = step()
+        log(f"warmup {i}: {info['t_total_s']*1e3:.1f} ms theta={info['theta']} "
+            f"num_rr={info['num_rr']}")
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        seeds, info = step()          # returns after the device work has completed
+        infos.append(info)
+    elapsed = time.perf_counter() - t0
+    for i, info in enumerate(infos):
+        log(f"step {i}: total {info['t_total_s']*1e3:.1f} ms gen {info['t_generate_s']*1e3:.1f} "
+            f"sel {info['t_select_s']*1e3:.1f} rr-kernel {info['t_rr_kernel_s']*1e3:.1f} ms "
+            f"({info['rr_kernel_launches']} launches)")
+    sets = sum(i["num_rr"] for i in infos)
+    edges = sum(i["edges_examined"] for i in infos)
+    k_time = sum(i["t_rr_kernel_s"] for i in infos)
+    k_launch = sum(i["rr_kernel_launches"] for i in infos)
+    philox = sum(i["edges_examined"] / 4.0 + i["num_rr"] for i in infos)
+    achieved = philox / k_time / 1e9
+    last = infos[-1]
+    out = {
+        "metric": METRIC,
+        "value": sets / elapsed,
+        "unit": "RR sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded R-MAT graph; no dataset)",
+        "config": describe(w),
+        "gteps": edges / elapsed / 1e9,
+        "s_per_query": elapsed / args.steps,
+        "theta": last["theta"],
+        "num_rr": last["num_rr"],
+        "lb": last["lb"],
+        "t_generate_s": sum(i["t_generate_s"] for i in infos) / args.steps,
+        "t_select_s": sum(i["t_select_s"] for i in infos) / args.steps,
+        "seeds_head": [int(s) for s in seeds[:5]],
+        "roofline": {
+            "kernel": "k_rr_ic (on-chip list)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_GPHILOX,
+            "unit": "Gphilox/s",
+            "frac": achieved / PEAK_GPHILOX,
+            "traffic": traffic_from_profile("rr_ic", args.workload),
+            "avg_launch_ms": k_time / k_launch * 1e3,
+            "philox_per_launch": philox / k_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

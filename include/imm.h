@@ -1,0 +1,178 @@
+/* imm.h -- C ABI of libimm: IMM influence maximisation on AMD Instinct MI355X (gfx950).
+ *
+ * The library generates random reverse-reachable (RR) sets on the GPU, keeps them
+ * resident in HBM, selects seeds by greedy maximum coverage on the GPU, and drives IMM's
+ * lower-bound / sample-size loop from the host.
+ *
+ * Method: S. Shahrouz, S. Salehkaleybar, M. Hashemi, "gIM: GPU Accelerated RIS-based
+ * Influence Maximization Algorithm" (IEEE TPDS; arXiv 2009.07325).  Passages are cited as
+ * "gIM Sec./Alg./Eq.".  Sample sizes follow IMM (Tang, Shi, Xiao, SIGMOD 2015), which gIM
+ * Alg. 2 defers to.
+ *
+ * Conventions
+ *  - Every function returns an imm_status; nothing is thrown across the ABI.  After a
+ *    non-OK status, imm_last_error() returns a thread-local description.
+ *  - Input arrays may be host or device pointers (the library copies them with
+ *    hipMemcpyDefault).  Output arrays named *_out are HOST pointers, owned by the caller.
+ *  - Graphs and pools are opaque, device-resident and owned by the library; each create
+ *    is paired with its destroy.  Calls on one object are not thread-safe; calls on
+ *    distinct objects are.
+ *  - `stream` arguments are hipStream_t values (NULL = the default stream).  Functions
+ *    that return host results synchronise that stream before returning.
+ *
+ * Random-number contract (what makes results reproducible bit for bit): Philox4x32-10
+ * (Salmon et al., SC'11) with key (seed mod 2^32, seed >> 32) and counter
+ * (r, g, 0, domain):
+ *    root of RR set r     : word 0 of counter (r, 0, 0, 1); root = (word * n) >> 32
+ *    IC test of in-edge e : word (e & 3) of counter (r, e >> 2, 0, 2)
+ *    LT draw at vertex v  : word 0 of counter (r, v, 0, 3)
+ * so RR set r is a pure function of (graph, model, seed, r), whatever the launch shape.
+ */
+#ifndef IMM_H
+#define IMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IMM_OK = 0,
+    IMM_EINVAL = 1,      /* an argument is out of range or inconsistent */
+    IMM_ENOMEM = 2,      /* device or host allocation failed */
+    IMM_ECAPACITY = 3,   /* a count exceeds what the format holds (e.g. RR index >= 2^32) */
+    IMM_EDEVICE = 4,     /* a HIP runtime call failed */
+    IMM_ENOTIMPL = 5,    /* the requested feature is not built */
+    IMM_EBUSY = 6,
+    IMM_ECANCELLED = 7
+} imm_status;
+
+/* Diffusion models, gIM Sec. II-B: independent cascade and linear threshold. */
+typedef enum { IMM_IC = 0, IMM_LT = 1 } imm_model;
+
+typedef struct imm_graph imm_graph;
+typedef struct imm_pool imm_pool;
+
+/* imm_graph_create flag: also build the LT encoding (lt_w may then be NULL, meaning unit
+ * raw weights, i.e. weighted-cascade LT with p(u,v) = 1/indeg(v)). */
+#define IMM_GRAPH_LT 0x1u
+
+typedef struct {
+    uint64_t seed;          /* Philox key of the RR pool */
+    int32_t fresh_final;    /* 0: the final sample reuses the estimation sets (IMM);
+                               1: the final theta sets are fresh indices after them */
+    int32_t reserved;
+    void* stream;           /* hipStream_t or NULL */
+} imm_options;
+
+typedef struct {
+    int64_t theta;          /* ceil(lambda* / LB) */
+    int64_t num_rr;         /* RR sets generated (pool size after the solve) */
+    int64_t covered;        /* sets covered by the returned seeds, in the final sample */
+    int64_t edges_examined; /* in-edges examined while generating, sum of member indegrees
+                               (imm_solve_pool: the pool's running total) */
+    int64_t pool_ids;       /* total members over all generated sets (same convention) */
+    int32_t phases;         /* greedy selections run (estimation phases + final) */
+    int32_t reserved;
+    double lb;              /* lower bound LB of OPT from gIM Alg. 2 (1.0 if no phase passes) */
+    double spread_est;      /* n * covered / |final sample|, the estimate of gIM Eq. 3 */
+    double lambda_prime;
+    double lambda_star;
+    double t_generate_s;    /* wall time in RR generation (device-synchronised) */
+    double t_select_s;      /* wall time in seed selection */
+    double t_total_s;
+    double t_rr_kernel_s;   /* summed duration of the RR-generation kernel launches
+                               (HIP events on the launch stream) */
+    int64_t rr_kernel_launches;
+} imm_info;
+
+/* Selects the HIP device used by subsequent calls from this thread. */
+imm_status imm_init(int32_t device);
+
+/* Thread-local message for the last non-OK status ("" if none). */
+const char* imm_last_error(void);
+
+/* Upload a directed graph G = (V, E), gIM Sec. II-A, as the CSR of its transpose
+ * (in-edges), and encode edge probabilities into 32-bit thresholds on the device.
+ *   n        vertices, n >= 2
+ *   m        edges, m >= 0
+ *   in_off   int64[n+1], in_off[0] = 0, non-decreasing, in_off[n] = m
+ *   in_src   int32[m], in_src[e] in [0, n): source u of in-edge e = (u, v) of vertex v
+ *   ic_p     float32[m] IC probabilities p_uv in [0, 1], or NULL (no IC support);
+ *            edge e is live when its draw x < floor(p * 2^32) (p = 1: always), the
+ *            comparison "p < p_uv" of gIM Alg. 3
+ *   lt_w     uint32[m] raw LT weights >= 1, normalised per vertex to sum 1 (gIM Sec.
+ *            II-B, Eq. 1), or NULL for unit weights; used only with IMM_GRAPH_LT
+ *   flags    IMM_GRAPH_LT or 0
+ * Arrays may be host or device memory; they are copied and may be freed after return.
+ * Errors: IMM_EINVAL for malformed arrays (checked on the device), IMM_ENOMEM. */
+imm_status imm_graph_create(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                            const float* ic_p, const uint32_t* lt_w, uint32_t flags,
+                            imm_graph** out);
+imm_status imm_graph_destroy(imm_graph* g);
+imm_status imm_graph_info(const imm_graph* g, int32_t* n, int64_t* m, int32_t* has_ic,
+                          int32_t* has_lt);
+
+/* Copy the device-side encodings back (for verification): thr uint32[m] (IC thresholds,
+ * NULL to skip) and cum uint32[m] (LT cumulative thresholds, NULL to skip). */
+imm_status imm_graph_export_encoding(const imm_graph* g, uint32_t* thr_out, uint32_t* cum_out);
+
+/* An RR pool: the RR sets of (graph, model, seed) with indices [0, size), kept in HBM
+ * (gIM Alg. 6 keeps all sets in one array RR with offsets).  Errors: IMM_EINVAL when the
+ * graph lacks the model's encoding. */
+imm_status imm_pool_create(const imm_graph* g, imm_model model, uint64_t seed, imm_pool** out);
+imm_status imm_pool_destroy(imm_pool* p);
+/* Number of sets, total members, and total in-edges examined so far. */
+imm_status imm_pool_size(const imm_pool* p, int64_t* num_sets, int64_t* num_ids,
+                         int64_t* edges_examined);
+
+/* Ensure RR sets [0, upto) exist, generating only the missing indices (gIM Alg. 3-6 for
+ * IC; Sec. III-G for LT).  Set r is every vertex that reaches its random root in the
+ * live-edge instance drawn for r (gIM Sec. II-E), whatever order it was generated in.
+ * Also maintains the pool's occurrence counts (Occur, gIM Sec. III-B).
+ * Errors: IMM_ECAPACITY if upto >= 2^32; IMM_ENOMEM. */
+imm_status imm_generate_rr(imm_pool* p, int64_t upto, void* stream);
+
+/* Canonical export of sets [first, first+count): off_out int64[count+1] (off_out[0] = 0)
+ * and ids_out int32[ids_cap] with each set's members sorted ascending.  If ids_cap is too
+ * small (or ids_out is NULL) only off_out and *ids_needed are written and IMM_ECAPACITY is
+ * returned (ids_out == NULL returns IMM_OK). */
+imm_status imm_rr_export(const imm_pool* p, int64_t first, int64_t count, int64_t* off_out,
+                         int32_t* ids_out, int64_t ids_cap, int64_t* ids_needed);
+
+/* Occurrence counts over sets [first, first+count): hist_out uint32[n], hist_out[v] =
+ * number of those sets containing v (gIM Sec. III-B "Occur"). */
+imm_status imm_rr_histogram(const imm_pool* p, int64_t first, int64_t count,
+                            uint32_t* hist_out);
+
+/* Greedy maximum coverage over sets [first, first+count), gIM Alg. 1 lines 6-10 with the
+ * max reduction of Sec. III-H and the cover/decrement of Alg. 7: k rounds, each taking the
+ * vertex outside S contained in the most uncovered sets (smallest id among ties) and
+ * removing the sets it covers.  seeds_out int32[k] in selection order; *covered_out = sets
+ * covered.  Requires 1 <= k <= n.  Runs on the device; synchronises `stream`. */
+imm_status imm_select_seeds(imm_pool* p, int64_t first, int64_t count, int32_t k,
+                            int32_t* seeds_out, int64_t* covered_out, void* stream);
+
+/* IMM on graph g (gIM Alg. 2 then Alg. 1): estimate LB, sample theta = lambda* / LB RR sets,
+ * select k seeds.  0 < eps < 1, ell > 0, 1 <= k <= n.  seeds_out int32[k].  The result is
+ * a pure function of (g, model, opt->seed, k, eps, ell, opt->fresh_final). */
+imm_status imm_solve(const imm_graph* g, int32_t k, double eps, double ell, imm_model model,
+                     const imm_options* opt, int32_t* seeds_out, imm_info* info);
+
+/* IMM against an existing pool (same graph/model/seed): consumes the pool's prefix and
+ * extends it only where needed, so repeated queries share RR sets.  Identical results to
+ * imm_solve with the pool's seed. */
+imm_status imm_solve_pool(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh_final,
+                          void* stream, int32_t* seeds_out, imm_info* info);
+
+/* IMM sample-size quantities, exposed for verification (IEEE double, no FMA contraction):
+ * ln C(n,k); lambda' of the LB loop; lambda* of the final sample; ell' = ell(1+ln2/ln n). */
+double imm_log_binom(int64_t n, int64_t k);
+double imm_lambda_prime(int64_t n, int64_t k, double eps, double ell);
+double imm_lambda_star(int64_t n, int64_t k, double eps, double ell);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMM_H */

@@ -1,0 +1,279 @@
+"""IMM influence maximisation on AMD Instinct MI355X: Python binding of libimm.
+
+Thin ctypes marshalling over the C ABI in include/imm.h; every step of the computation
+runs in the library's HIP kernels.  The binding keeps the ABI's function names.  Arrays
+are numpy arrays (host) or objects exposing ``data_ptr()`` (e.g. torch CUDA tensors).
+
+Loading fails loudly when libimm.so has not been built (``python -m
+paper_2009_07325_amd.build``); there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimm.so")
+
+IMM_IC, IMM_LT = 0, 1
+IMM_GRAPH_LT = 0x1
+STATUS = {0: "IMM_OK", 1: "IMM_EINVAL", 2: "IMM_ENOMEM", 3: "IMM_ECAPACITY", 4: "IMM_EDEVICE",
+          5: "IMM_ENOTIMPL", 6: "IMM_EBUSY", 7: "IMM_ECANCELLED"}
+
+# every entry point declared in include/imm.h
+EXPORTS = ("imm_init", "imm_last_error", "imm_graph_create", "imm_graph_destroy",
+           "imm_graph_info", "imm_graph_export_encoding", "imm_pool_create", "imm_pool_destroy",
+           "imm_pool_size", "imm_generate_rr", "imm_rr_export", "imm_rr_histogram",
+           "imm_select_seeds", "imm_solve", "imm_solve_pool", "imm_log_binom",
+           "imm_lambda_prime", "imm_lambda_star")
+
+
+class ImmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class ImmOptions(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("fresh_final", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class ImmInfo(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_int64), ("num_rr", ctypes.c_int64),
+                ("covered", ctypes.c_int64), ("edges_examined", ctypes.c_int64),
+                ("pool_ids", ctypes.c_int64), ("phases", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lb", ctypes.c_double),
+                ("spread_est", ctypes.c_double), ("lambda_prime", ctypes.c_double),
+                ("lambda_star", ctypes.c_double), ("t_generate_s", ctypes.c_double),
+                ("t_select_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
+                ("t_rr_kernel_s", ctypes.c_double), ("rr_kernel_launches", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libimm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2009_07325_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, u32, u64, dbl, p = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p)
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "imm_init": [i32],
+            "imm_graph_create": [i32, i64, p, p, p, p, u32, pp],
+            "imm_graph_destroy": [p],
+            "imm_graph_info": [p, p, p, p, p],
+            "imm_graph_export_encoding": [p, p, p],
+            "imm_pool_create": [p, ctypes.c_int, u64, pp],
+            "imm_pool_destroy": [p],
+            "imm_pool_size": [p, p, p, p],
+            "imm_generate_rr": [p, i64, p],
+            "imm_rr_export": [p, i64, i64, p, p, i64, p],
+            "imm_rr_histogram": [p, i64, i64, p],
+            "imm_select_seeds": [p, i64, i64, i32, p, p, p],
+            "imm_solve": [p, i32, dbl, dbl, ctypes.c_int, ctypes.POINTER(ImmOptions), p,
+                          ctypes.POINTER(ImmInfo)],
+            "imm_solve_pool": [p, i32, dbl, dbl, i32, p, p, ctypes.POINTER(ImmInfo)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.imm_last_error.argtypes = []
+        L.imm_last_error.restype = ctypes.c_char_p
+        L.imm_log_binom.argtypes = [i64, i64]
+        L.imm_log_binom.restype = dbl
+        for name in ("imm_lambda_prime", "imm_lambda_star"):
+            f = getattr(L, name)
+            f.argtypes = [i64, i64, dbl, dbl]
+            f.restype = dbl
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise ImmError(status, lib().imm_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ---- entry points (same names as the C ABI) ------------------------------------------
+def imm_init(device: int = 0) -> None:
+    _check(lib().imm_init(device))
+
+
+def imm_last_error() -> str:
+    return lib().imm_last_error().decode(errors="replace")
+
+
+def imm_graph_create(n: int, in_off, in_src, ic_p=None, lt_w=None, flags: int = 0):
+    """Returns an opaque graph handle (ctypes.c_void_p)."""
+    def host(a, dt):
+        if a is None or hasattr(a, "data_ptr"):
+            return a
+        return np.ascontiguousarray(a, dtype=dt)
+    in_off = host(in_off, np.int64)
+    in_src = host(in_src, np.int32)
+    ic_p = host(ic_p, np.float32)
+    lt_w = host(lt_w, np.uint32)
+    m = int(in_src.numel() if hasattr(in_src, "numel") else len(in_src))
+    out = ctypes.c_void_p()
+    _check(lib().imm_graph_create(n, m, _ptr(in_off), _ptr(in_src), _ptr(ic_p), _ptr(lt_w),
+                                  flags, ctypes.byref(out)))
+    return out
+
+
+def imm_graph_destroy(g) -> None:
+    _check(lib().imm_graph_destroy(g))
+
+
+def imm_graph_info(g) -> dict:
+    n, m, ic, lt = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().imm_graph_info(g, ctypes.byref(n), ctypes.byref(m), ctypes.byref(ic),
+                                ctypes.byref(lt)))
+    return dict(n=n.value, m=m.value, has_ic=bool(ic.value), has_lt=bool(lt.value))
+
+
+def imm_graph_export_encoding(g, ic: bool = True, lt: bool = False):
+    info = imm_graph_info(g)
+    thr = np.zeros(info["m"], dtype=np.uint32) if ic else None
+    cum = np.zeros(info["m"], dtype=np.uint32) if lt else None
+    _check(lib().imm_graph_export_encoding(g, _ptr(thr), _ptr(cum)))
+    return thr, cum
+
+
+def imm_pool_create(g, model: int, seed: int):
+    out = ctypes.c_void_p()
+    _check(lib().imm_pool_create(g, model, seed, ctypes.byref(out)))
+    return out
+
+
+def imm_pool_destroy(p) -> None:
+    _check(lib().imm_pool_destroy(p))
+
+
+def imm_pool_size(p) -> tuple[int, int, int]:
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().imm_pool_size(p, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def imm_generate_rr(p, upto: int, stream=None) -> None:
+    _check(lib().imm_generate_rr(p, upto, _stream(stream)))
+
+
+def imm_rr_export(p, first: int, count: int) -> tuple[np.ndarray, np.ndarray]:
+    off = np.zeros(count + 1, dtype=np.int64)
+    need = ctypes.c_int64()
+    _check(lib().imm_rr_export(p, first, count, _ptr(off), None, 0, ctypes.byref(need)))
+    ids = np.zeros(max(need.value, 1), dtype=np.int32)
+    _check(lib().imm_rr_export(p, first, count, _ptr(off), _ptr(ids), len(ids),
+                               ctypes.byref(need)))
+    return off, ids[:need.value]
+
+
+def imm_rr_histogram(p, first: int, count: int, n: int) -> np.ndarray:
+    h = np.zeros(n, dtype=np.uint32)
+    _check(lib().imm_rr_histogram(p, first, count, _ptr(h)))
+    return h
+
+
+def imm_select_seeds(p, first: int, count: int, k: int, stream=None) -> tuple[np.ndarray, int]:
+    seeds = np.zeros(k, dtype=np.int32)
+    cov = ctypes.c_int64()
+    _check(lib().imm_select_seeds(p, first, count, k, _ptr(seeds), ctypes.byref(cov),
+                                  _stream(stream)))
+    return seeds, cov.value
+
+
+def imm_solve(g, k: int, eps: float, ell: float, model: int, seed: int,
+              fresh_final: bool = False, stream=None) -> tuple[np.ndarray, dict]:
+    opt = ImmOptions(seed=seed, fresh_final=int(fresh_final), reserved=0,
+                     stream=_stream(stream))
+    seeds = np.zeros(k, dtype=np.int32)
+    info = ImmInfo()
+    _check(lib().imm_solve(g, k, eps, ell, model, ctypes.byref(opt), _ptr(seeds),
+                           ctypes.byref(info)))
+    return seeds, info.as_dict()
+
+
+def imm_solve_pool(p, k: int, eps: float, ell: float, fresh_final: bool = False,
+                   stream=None) -> tuple[np.ndarray, dict]:
+    seeds = np.zeros(k, dtype=np.int32)
+    info = ImmInfo()
+    _check(lib().imm_solve_pool(p, k, eps, ell, int(fresh_final), _stream(stream), _ptr(seeds),
+                                ctypes.byref(info)))
+    return seeds, info.as_dict()
+
+
+def imm_log_binom(n: int, k: int) -> float:
+    return lib().imm_log_binom(n, k)
+
+
+def imm_lambda_prime(n: int, k: int, eps: float, ell: float) -> float:
+    return lib().imm_lambda_prime(n, k, eps, ell)
+
+
+def imm_lambda_star(n: int, k: int, eps: float, ell: float) -> float:
+    return lib().imm_lambda_star(n, k, eps, ell)
+
+
+@dataclass
+class Graph:
+    """Owning wrapper of a device graph (destroyed with the object)."""
+    handle: ctypes.c_void_p
+    n: int
+    m: int
+
+    @classmethod
+    def from_arrays(cls, n, in_off, in_src, ic_p=None, lt_w=None, lt: bool = False) -> "Graph":
+        h = imm_graph_create(n, in_off, in_src, ic_p, lt_w, IMM_GRAPH_LT if lt else 0)
+        return cls(h, n, int(len(in_src)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.imm_graph_destroy(self.handle)
+            self.handle = None
+
+
+@dataclass
+class Pool:
+    """Owning wrapper of a device RR pool."""
+    handle: ctypes.c_void_p
+    graph: Graph
+
+    @classmethod
+    def create(cls, graph: Graph, model: int, seed: int) -> "Pool":
+        return cls(imm_pool_create(graph.handle, model, seed), graph)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.imm_pool_destroy(self.handle)
+            self.handle = None

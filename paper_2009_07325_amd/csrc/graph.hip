@@ -1,0 +1,154 @@
+// Graph upload checks and threshold encodings (run once per graph, on the device).
+//
+// IC (gIM Sec. II-B; Alg. 3 tests "p < p_uv"): edge e is live for RR set r when its 32-bit
+// draw x satisfies x < floor(p_e * 2^32); p = 1 saturates to kAlways ("always live").
+// For a float32 p, p * 2^32 is exact in double, so the floor is exact.
+// LT (gIM Sec. II-B Eq. 1, Sec. III-G): a vertex activates through at most one in-edge,
+// edge j with probability w_j / sum(w).  We store the scaled prefix sums
+// floor(S_j * 2^32 / T) and saturate the last one, so the first entry above a uniform
+// draw names the chosen in-edge.
+#include "kernels.hpp"
+
+namespace imm {
+
+__global__ void k_validate_off(int32_t n, int64_t m, const int64_t* __restrict__ off,
+                               uint32_t* err) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > n) return;
+    bool bad = false;
+    if (v == 0 && off[0] != 0) bad = true;
+    if (v == n && off[n] != m) bad = true;
+    if (v < n && off[v + 1] < off[v]) bad = true;
+    if (bad) atomicOr(err, 1u);
+}
+
+__global__ void k_validate_edges(int32_t n, int64_t m, const int32_t* __restrict__ src,
+                                 const float* __restrict__ p, const uint32_t* __restrict__ w,
+                                 uint32_t* err) {
+    uint32_t bits = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = src[e];
+        if (s < 0 || s >= n) bits |= 2u;
+        if (p) {
+            float q = p[e];
+            if (!(q >= 0.0f && q <= 1.0f)) bits |= 4u;
+        }
+        if (w && w[e] == 0u) bits |= 8u;
+    }
+    if (bits) atomicOr(err, bits);
+}
+
+hipError_t launch_validate(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                           const float* ic_p, const uint32_t* lt_w, uint32_t* err,
+                           hipStream_t s) {
+    k_validate_off<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(n, m, in_off, err);
+    if (m > 0) {
+        int64_t blocks = (m + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        k_validate_edges<<<(unsigned)blocks, 256, 0, s>>>(n, m, in_src, ic_p, lt_w, err);
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_encode_ic(int64_t m, const float* __restrict__ p, uint32_t* __restrict__ thr) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double t = floor((double)p[e] * 4294967296.0);
+        thr[e] = t >= 4294967296.0 ? kAlways : (uint32_t)t;
+    }
+}
+
+hipError_t launch_encode_ic(int64_t m, const float* p, uint32_t* thr, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    k_encode_ic<<<(unsigned)blocks, 256, 0, s>>>(m, p, thr);
+    return hipGetLastError();
+}
+
+// One wave per vertex: record (start, degree) and detect a common IC threshold.
+__global__ void k_build_vrec(int32_t n, const int64_t* __restrict__ off,
+                             const uint32_t* __restrict__ thr, VRec* __restrict__ vrec,
+                             unsigned int* n_mixed) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        int64_t s = off[v], e = off[v + 1];
+        uint32_t deg = (uint32_t)(e - s);
+        bool uniform = thr != nullptr;
+        uint32_t t0 = 0;
+        if (thr && e > s) {
+            t0 = thr[s];
+            bool same = true;
+            for (int64_t j = s + lane; j < e; j += kWave) same &= thr[j] == t0;
+            uniform = ballot(!same) == 0;
+        }
+        if (lane == 0) {
+            VRec rec;
+            rec.start = s;
+            rec.deg = deg | (uniform ? kUniformBit : 0u);
+            rec.thr = t0;
+            vrec[v] = rec;
+            if (!uniform && thr) atomicAdd(n_mixed, 1u);
+        }
+    }
+}
+
+hipError_t launch_build_vrec(int32_t n, const int64_t* in_off, const uint32_t* thr, VRec* vrec,
+                             unsigned int* n_mixed, hipStream_t s) {
+    int64_t blocks = ((int64_t)n * kWave + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_build_vrec<<<(unsigned)blocks, 256, 0, s>>>(n, in_off, thr, vrec, n_mixed);
+    return hipGetLastError();
+}
+
+// floor(num * 2^32 / den) for num < den < 2^63, by 32 steps of restoring binary division.
+__device__ __forceinline__ uint32_t scaled_ratio(uint64_t num, uint64_t den) {
+    uint64_t rem = num;
+    uint32_t q = 0;
+    for (int i = 0; i < 32; ++i) {
+        rem <<= 1;
+        q <<= 1;
+        if (rem >= den) {
+            rem -= den;
+            q |= 1u;
+        }
+    }
+    return q;
+}
+
+// One wave per vertex: total weight by a wave reduction, then the scaled prefix sums
+// chunk by chunk (64 edges per step, a wave scan per chunk).
+__global__ void k_encode_lt(int32_t n, const int64_t* __restrict__ off,
+                            const uint32_t* __restrict__ w, uint32_t* __restrict__ cum) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        const int64_t s = off[v], e = off[v + 1];
+        if (e == s) continue;
+        uint64_t part = 0;
+        for (int64_t j = s + lane; j < e; j += kWave) part += w ? (uint64_t)w[j] : 1ull;
+        const uint64_t total = wave_sum(part);
+        uint64_t carry = 0;
+        for (int64_t base = s; base < e; base += kWave) {
+            const int64_t j = base + lane;
+            uint64_t wj = (j < e) ? (w ? (uint64_t)w[j] : 1ull) : 0ull;
+            uint64_t incl = wave_incl_scan(wj) + carry;
+            if (j < e) cum[j] = (j == e - 1) ? kAlways : scaled_ratio(incl, total);
+            carry = __shfl(incl, kWave - 1, kWave);
+        }
+    }
+}
+
+hipError_t launch_encode_lt(int32_t n, const int64_t* in_off, const uint32_t* w, uint32_t* cum,
+                            hipStream_t s) {
+    int64_t blocks = ((int64_t)n * kWave + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_encode_lt<<<(unsigned)blocks, 256, 0, s>>>(n, in_off, w, cum);
+    return hipGetLastError();
+}
+
+}  // namespace imm

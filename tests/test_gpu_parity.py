@@ -1,0 +1,178 @@
+"""GPU parity: every result of the HIP path equals the CPU oracle's, bit for bit.
+
+Integer results (thresholds, RR sets, occurrence counts, seeds, covered counts, edge counts)
+and the double-precision IMM quantities (lambda', lambda*, LB, theta) are compared exactly:
+under the shared Philox contract there is exactly one correct answer.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs, graphs
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_graph(imm, g, ic_p=None, lt_w=None, lt=False):
+    return imm.Graph.from_arrays(g.n, g.in_off, g.in_src, ic_p=ic_p, lt_w=lt_w, lt=lt)
+
+
+def _compare_pool(imm, g, model, seed, count, ic_p=None, lt_w=None, chunks=None):
+    gg = _gpu_graph(imm, g, ic_p=ic_p, lt_w=lt_w, lt=(model == imm.IMM_LT))
+    pool = imm.Pool.create(gg, model, seed)
+    for upto in (chunks or [count]):
+        imm.imm_generate_rr(pool.handle, upto)
+    off_g, ids_g = imm.imm_rr_export(pool.handle, 0, count)
+    ref = oracle.Pool(g, model, seed, ic_p=ic_p, lt_w=lt_w)
+    ref.extend(count)
+    off_o, ids_o = ref.export()
+    assert np.array_equal(off_g, off_o), "set sizes differ"
+    assert np.array_equal(ids_g, ids_o), "set members differ"
+    hist_g = imm.imm_rr_histogram(pool.handle, 0, count, g.n)
+    assert np.array_equal(hist_g, ref.hist())
+    n_sets, n_ids, edges = imm.imm_pool_size(pool.handle)
+    assert n_sets == count and n_ids == ref.total() and edges == ref.edges()
+    return pool, ref
+
+
+def test_ic_encoding_matches_oracle(imm_gpu):
+    g = graphs.erdos_renyi(3000, 40_000, seed=11)
+    rng = np.random.default_rng(5)
+    p = rng.random(g.m).astype(np.float32)
+    p[::7] = 0.0
+    p[::11] = 1.0
+    p[::13] = np.float32(1.0) - np.float32(2.0 ** -24)
+    p[::17] = np.float32(2.0 ** -40)
+    gg = _gpu_graph(imm_gpu, g, ic_p=p)
+    thr, _ = imm_gpu.imm_graph_export_encoding(gg.handle, ic=True)
+    assert np.array_equal(thr, oracle.encode_ic(p))
+
+
+def test_wc_encoding_full_size_c2(imm_gpu):
+    w = configs.c2()
+    gg = _gpu_graph(imm_gpu, w.graph, ic_p=w.ic_p)
+    thr, _ = imm_gpu.imm_graph_export_encoding(gg.handle, ic=True)
+    assert np.array_equal(thr, oracle.encode_ic(w.ic_p))
+
+
+@pytest.mark.parametrize("unit", [False, True])
+def test_lt_encoding_matches_oracle(imm_gpu, unit):
+    g = graphs.rmat(12, 60_000, seed=21)
+    w = None if unit else graphs.lt_uniform_weights(g, seed=22)
+    gg = _gpu_graph(imm_gpu, g, lt_w=w, lt=True)
+    _, cum = imm_gpu.imm_graph_export_encoding(gg.handle, ic=False, lt=True)
+    assert np.array_equal(cum, oracle.encode_lt(g.in_off, w))
+
+
+def test_rr_sets_ic_c1(imm_gpu):
+    w = configs.c1()
+    _compare_pool(imm_gpu, w.graph, imm_gpu.IMM_IC, w.seed, 6000, ic_p=w.ic_p)
+
+
+def test_rr_sets_ic_rmat_wc_chunked(imm_gpu):
+    g = graphs.rmat(15, 16 << 15, seed=31)
+    p = graphs.weighted_cascade(g)
+    _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 0xABCDEF0123, 30_000, ic_p=p,
+                  chunks=[1, 777, 10_000, 30_000])
+
+
+def test_rr_sets_ic_per_edge_thresholds(imm_gpu):
+    g = graphs.rmat(13, 12 << 13, seed=41)
+    p = graphs.trivalency(g, seed=42)
+    p[::5] = np.float32(0.5)
+    _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 99, 20_000, ic_p=p)
+
+
+def test_rr_sets_ic_big_sets(imm_gpu):
+    """p = 1 everywhere on a dense ER graph: RR(r) = all ancestors of the root, thousands
+    of vertices, beyond the on-chip member list, so the HBM big-set path runs."""
+    g = graphs.erdos_renyi(5000, 50_000, seed=51)
+    p = np.ones(g.m, dtype=np.float32)
+    pool, ref = _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 7, 300, ic_p=p)
+    off, _ = ref.export()
+    assert np.diff(off).max() > 2048
+
+
+@pytest.mark.parametrize("unit", [False, True])
+def test_rr_sets_lt(imm_gpu, unit):
+    g = graphs.rmat(14, 16 << 14, seed=61)
+    w = None if unit else graphs.lt_uniform_weights(g, seed=62)
+    _compare_pool(imm_gpu, g, imm_gpu.IMM_LT, 0x5EED0003, 40_000, lt_w=w,
+                  chunks=[5, 40_000])
+
+
+def test_rr_sets_lt_long_walks(imm_gpu):
+    """A functional graph (one in-edge per vertex, a long cycle plus hubs) gives long walks
+    and exercises the search over long in-lists."""
+    n = 6000
+    src = list(range(1, n)) + [0]
+    dst = list(range(0, n - 1)) + [n - 1]
+    rng = np.random.default_rng(3)
+    hubs = rng.integers(0, n, 200)
+    for h in hubs:          # vertex h gets many in-edges -> long in-lists
+        for u in rng.choice(n, 300, replace=False):
+            if u != h and u != (h + 1) % n:
+                src.append(int(u)); dst.append(int(h))
+    g = graphs.from_edges(n, src, dst)
+    w = graphs.lt_uniform_weights(g, seed=64)
+    _compare_pool(imm_gpu, g, imm_gpu.IMM_LT, 1234, 3000, lt_w=w)
+
+
+@pytest.mark.parametrize("first,count,k", [(0, 5000, 10), (1000, 3000, 25), (0, 5000, 1000)])
+def test_select_matches_oracle(imm_gpu, first, count, k):
+    w = configs.c1()
+    gg = _gpu_graph(imm_gpu, w.graph, ic_p=w.ic_p)
+    pool = imm_gpu.Pool.create(gg, imm_gpu.IMM_IC, w.seed)
+    imm_gpu.imm_generate_rr(pool.handle, first + count)
+    seeds_g, cov_g = imm_gpu.imm_select_seeds(pool.handle, first, count, k)
+    ref = oracle.Pool(w.graph, oracle.IC, w.seed, ic_p=w.ic_p)
+    ref.extend(first + count)
+    seeds_o, cov_o = ref.greedy(k, first, count)
+    assert np.array_equal(seeds_g, seeds_o)
+    assert cov_g == cov_o
+    assert len(set(seeds_g.tolist())) == k
+
+
+def _solve_both(imm, g, model, k, eps, ell, seed, ic_p=None, lt_w=None, fresh=False):
+    gg = _gpu_graph(imm, g, ic_p=ic_p, lt_w=lt_w, lt=(model == imm.IMM_LT))
+    seeds_g, info = imm.imm_solve(gg.handle, k, eps, ell, model, seed, fresh_final=fresh)
+    ref = oracle.imm_solve(g, model, k, eps, ell, seed, ic_p=ic_p, lt_w=lt_w, fresh_final=fresh)
+    assert np.array_equal(seeds_g, ref["seeds"])
+    for key in ("theta", "num_rr", "covered", "phases"):
+        assert info[key] == ref[key], key
+    assert info["edges_examined"] == ref["edges"]
+    assert info["pool_ids"] == ref["pool_ids"]
+    assert info["lb"] == ref["lb"]
+    assert info["spread_est"] == ref["spread_est"]
+    assert info["lambda_prime"] == ref["lambda_prime"]
+    assert info["lambda_star"] == ref["lambda_star"]
+    return seeds_g, info, ref
+
+
+def test_solve_c1_matches_oracle(imm_gpu):
+    w = configs.c1()
+    _solve_both(imm_gpu, w.graph, imm_gpu.IMM_IC, w.k, w.eps, w.ell, w.seed, ic_p=w.ic_p)
+
+
+def test_solve_c1_fresh_final_matches_oracle(imm_gpu):
+    w = configs.c1()
+    _solve_both(imm_gpu, w.graph, imm_gpu.IMM_IC, w.k, w.eps, w.ell, w.seed, ic_p=w.ic_p,
+                fresh=True)
+
+
+def test_solve_lt_small_matches_oracle(imm_gpu):
+    g = graphs.rmat(12, 16 << 12, seed=71)
+    w = graphs.lt_uniform_weights(g, seed=72)
+    _solve_both(imm_gpu, g, imm_gpu.IMM_LT, 20, 0.3, 1.0, 0x5EED0003, lt_w=w)
+
+
+def test_solve_pool_prefix_reuse(imm_gpu):
+    """Queries against one shared pool return what independent solves return."""
+    w = configs.c1()
+    gg = _gpu_graph(imm_gpu, w.graph, ic_p=w.ic_p)
+    pool = imm_gpu.Pool.create(gg, imm_gpu.IMM_IC, w.seed)
+    for k, eps in [(10, 0.5), (5, 0.3), (20, 0.5), (10, 0.5)]:
+        s_pool, i_pool = imm_gpu.imm_solve_pool(pool.handle, k, eps, 1.0)
+        s_alone, i_alone = imm_gpu.imm_solve(gg.handle, k, eps, 1.0, imm_gpu.IMM_IC, w.seed)
+        assert np.array_equal(s_pool, s_alone)
+        assert i_pool["theta"] == i_alone["theta"] and i_pool["covered"] == i_alone["covered"]
