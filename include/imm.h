@@ -82,9 +82,13 @@ typedef struct {
     double t_generate_s;    /* wall time in RR generation (device-synchronised) */
     double t_select_s;      /* wall time in seed selection */
     double t_total_s;
-    double t_rr_kernel_s;   /* summed duration of the RR-generation kernel launches
-                               (HIP events on the launch stream) */
+    double t_rr_kernel_s;   /* summed duration of the light RR-generation launches (IC: one
+                               wave per set; LT: the walk kernel), HIP events on the stream */
     int64_t rr_kernel_launches;
+    double t_rr_heavy_s;    /* same for the heavy launches (IC: one workgroup per set with
+                               hub-heavy work; LT: walks too long for the on-chip list) */
+    int64_t rr_heavy_launches;
+    int64_t edges_heavy;    /* part of edges_examined in sets finished by the heavy launches */
 } imm_info;
 
 /* Selects the HIP device used by subsequent calls from this thread. */

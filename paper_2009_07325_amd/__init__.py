@@ -50,7 +50,9 @@ class ImmInfo(ctypes.Structure):
                 ("spread_est", ctypes.c_double), ("lambda_prime", ctypes.c_double),
                 ("lambda_star", ctypes.c_double), ("t_generate_s", ctypes.c_double),
                 ("t_select_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
-                ("t_rr_kernel_s", ctypes.c_double), ("rr_kernel_launches", ctypes.c_int64)]
+                ("t_rr_kernel_s", ctypes.c_double), ("rr_kernel_launches", ctypes.c_int64),
+                ("t_rr_heavy_s", ctypes.c_double), ("rr_heavy_launches", ctypes.c_int64),
+                ("edges_heavy", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

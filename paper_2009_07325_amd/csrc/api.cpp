@@ -5,7 +5,9 @@
 // sample/selection (gIM Alg. 1) on the host in IEEE double.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -129,15 +131,18 @@ struct imm_pool {
     PoolCounters* host_ctr = nullptr;   // pinned mirror
 
     int64_t cap_lists = 0;
-    uint32_t* ovf_list = nullptr;
-    uint32_t* cap_list = nullptr;
+    uint32_t* heavy_list = nullptr;     // light -> heavy queue
+    uint32_t* cap_list = nullptr;       // id-buffer capacity misses
     uint32_t* retry_list = nullptr;
 
-    int grid = 0, grid_big_max = 0;
+    int grid = 0;                       // light launch: blocks of 256 threads
     int64_t vis_words = 0;
-    uint32_t* visited = nullptr;
-    int64_t big_slots = 0;
-    int32_t* big_list = nullptr;
+    uint32_t* visited = nullptr;        // grid * 4 bitmaps
+    int64_t hslots = 0;                 // heavy slots (IC: workgroups, LT: waves)
+    uint32_t* hvisited = nullptr;
+    int32_t* hlist = nullptr;
+    int64_t budget = 4096;              // light-wave group budget per set
+    int heavy_block = 256;              // threads per heavy set (256 or 1024)
 
     // selection workspace
     int32_t* h = nullptr;
@@ -158,9 +163,17 @@ struct imm_pool {
 
     // HIP events bracketing each RR-generation kernel launch
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double kernel_s = 0.0;
+    double kernel_s = 0.0;               // light kernel (IC) / walk kernel (LT)
     int64_t kernel_launches = 0;
+    double heavy_s = 0.0;                // heavy kernel (IC) / HBM-list walk kernel (LT)
+    int64_t heavy_launches = 0;
 };
+
+static unsigned long long sum64(const unsigned long long* v) {
+    unsigned long long t = 0;
+    for (int i = 0; i < 64; ++i) t += v[i];
+    return t;
+}
 
 // ------------------------------------------------------------------------------------
 // IMM sample sizes (Tang, Shi, Xiao 2015; gIM Alg. 2 defers f(n, eps, k) and theta to
@@ -378,11 +391,12 @@ extern "C" imm_status imm_pool_destroy(imm_pool* p) {
     dfree(p->hist);
     dfree(p->ctr);
     if (p->host_ctr) (void)hipHostFree(p->host_ctr);
-    dfree(p->ovf_list);
+    dfree(p->heavy_list);
     dfree(p->cap_list);
     dfree(p->retry_list);
     dfree(p->visited);
-    dfree(p->big_list);
+    dfree(p->hvisited);
+    dfree(p->hlist);
     dfree(p->h);
     dfree(p->hist_tmp);
     dfree(p->inv_off);
@@ -404,9 +418,12 @@ extern "C" imm_status imm_pool_destroy(imm_pool* p) {
 static imm_status pool_init(imm_pool* p) {
     const imm_graph* g = p->g;
     const bool lt = p->model == IMM_LT;
-    const int bpc = rr_blocks_per_cu(lt, false);
-    p->grid = g->cus * bpc;
+    p->grid = g->cus * gen_blocks_per_cu(lt ? 2 : 0);
     p->vis_words = ((int64_t)g->n + 31) / 32;
+    // light visited bitmaps: at most ~4 GiB (fewer resident blocks on huge graphs)
+    const int64_t vis_bytes_per_block = 4 * p->vis_words * 4;
+    const int64_t max_blocks = std::max<int64_t>(g->cus, ((int64_t)4 << 30) / vis_bytes_per_block);
+    if (p->grid > max_blocks) p->grid = (int)max_blocks;
     IMM_TRY(dalloc(&p->hist, g->n));
     IMM_TRY(dalloc(&p->ctr, 1));
     IMM_TRY(dalloc(&p->visited, (int64_t)p->grid * 4 * p->vis_words));
@@ -418,6 +435,8 @@ static imm_status pool_init(imm_pool* p) {
     memset(p->host_ctr, 0, sizeof(PoolCounters));
     HIP_TRY(hipEventCreate(&p->ev0));
     HIP_TRY(hipEventCreate(&p->ev1));
+    if (const char* b = getenv("IMM_LIGHT_BUDGET")) p->budget = std::max(1ll, atoll(b));
+    if (const char* b = getenv("IMM_HEAVY_BLOCK")) p->heavy_block = atoi(b) == 1024 ? 1024 : 256;
     return IMM_OK;
 }
 
@@ -454,8 +473,8 @@ extern "C" imm_status imm_pool_size(const imm_pool* p, int64_t* num_sets, int64_
     PoolCounters c;
     HIP_TRY(hipMemcpy(&c, p->ctr, sizeof c, hipMemcpyDeviceToHost));
     if (num_sets) *num_sets = p->count;
-    if (num_ids) *num_ids = (int64_t)c.placed;
-    if (edges_examined) *edges_examined = (int64_t)c.edges;
+    if (num_ids) *num_ids = (int64_t)sum64(c.placed);
+    if (edges_examined) *edges_examined = (int64_t)(sum64(c.edges) + sum64(c.hedges));
     return IMM_OK;
 }
 
@@ -469,63 +488,91 @@ static GenArgs gen_args(imm_pool* p) {
     a.n = g->n;
     a.k0 = (uint32_t)p->seed;
     a.k1 = (uint32_t)(p->seed >> 32);
+    a.budget = p->budget;
+    a.heavy_list = p->heavy_list;
     a.ids = p->ids;
     a.cap_ids = p->cap_ids;
     a.rr_start = p->rr_start;
     a.rr_len = p->rr_len;
     a.hist = p->hist;
     a.ctr = p->ctr;
-    a.ovf_list = p->ovf_list;
     a.cap_list = p->cap_list;
     a.visited = p->visited;
+    a.hvisited = p->hvisited;
     a.vis_words = p->vis_words;
-    a.big_list = p->big_list;
+    a.hlist = p->hlist;
     return a;
 }
 
-// Zero the per-launch counters (work cursor, deferral and capacity counts).
-static imm_status reset_launch_counters(imm_pool* p, hipStream_t s) {
-    HIP_TRY(hipMemsetAsync(&p->ctr->work, 0, sizeof(unsigned long long), s));
-    HIP_TRY(hipMemsetAsync(&p->ctr->n_overflow, 0, 2 * sizeof(unsigned int), s));
-    return IMM_OK;
+static double elapsed_s(imm_pool* p) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p->ev0, p->ev1) != hipSuccess) return 0.0;
+    return ms * 1e-3;
 }
 
-static imm_status run_gen(imm_pool* p, bool big, int64_t first, int64_t count,
-                          const uint32_t* list, hipStream_t s) {
-    IMM_TRY(reset_launch_counters(p, s));
+// Light launch over RR indices first + i (or list[i]), i < count.
+static imm_status run_light(imm_pool* p, int64_t first, int64_t count, const uint32_t* list,
+                            hipStream_t s) {
+    HIP_TRY(hipMemsetAsync(&p->ctr->work, 0, sizeof(unsigned long long), s));
+    HIP_TRY(hipMemsetAsync(&p->ctr->n_heavy, 0, 2 * sizeof(unsigned int), s));
     GenArgs a = gen_args(p);
     a.first = first;
     a.count = count;
     a.list = list;
-    int grid = p->grid;
-    if (big) {
-        int64_t want = (count + 3) / 4;
-        grid = (int)(want < p->grid_big_max ? want : p->grid_big_max);
-        if (grid < 1) grid = 1;
-    }
+    int64_t grid = std::min<int64_t>(p->grid, (count + 3) / 4);
+    if (grid < 1) grid = 1;
     HIP_TRY(hipEventRecord(p->ev0, s));
-    if (p->model == IMM_IC) HIP_TRY(launch_rr_ic(a, big, grid, s));
-    else HIP_TRY(launch_rr_lt(a, big, grid, s));
+    if (p->model == IMM_IC) HIP_TRY(launch_ic_light(a, (int)grid, s));
+    else HIP_TRY(launch_lt(a, false, (int)grid, s));
     HIP_TRY(hipEventRecord(p->ev1, s));
     IMM_TRY(read_counters(p, s));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-    p->kernel_s += ms * 1e-3;
+    p->kernel_s += elapsed_s(p);
     p->kernel_launches += 1;
     return IMM_OK;
 }
 
-static imm_status ensure_big(imm_pool* p) {
-    if (p->big_list) return IMM_OK;
+static imm_status ensure_heavy(imm_pool* p) {
+    if (p->hlist) return IMM_OK;
     const int64_t n = p->g->n;
-    // member lists of n entries per wave slot; bounded to ~2 GiB and to the small grid
-    int64_t slots = ((int64_t)2 << 30) / (4 * n);
-    if (slots > (int64_t)p->grid * 4) slots = (int64_t)p->grid * 4;
-    if (slots < 4) slots = 4;
-    slots = (slots / 4) * 4;
-    IMM_TRY(dalloc(&p->big_list, slots * n));
-    p->big_slots = slots;
-    p->grid_big_max = (int)(slots / 4);
+    const bool lt = p->model == IMM_LT;
+    // slots: IC one per 1024-thread workgroup, LT one per wave; lists of n entries each,
+    // bounded to ~4 GiB of lists
+    int64_t want = lt ? (int64_t)p->g->cus * gen_blocks_per_cu(3) * 4
+                      : (int64_t)p->g->cus * gen_blocks_per_cu(p->heavy_block == 1024 ? 1 : 4);
+    int64_t cap = std::max<int64_t>(4, ((int64_t)4 << 30) / (4 * n + 4 * p->vis_words));
+    int64_t slots = std::min(want, cap);
+    if (lt) slots = std::max<int64_t>(4, (slots / 4) * 4);
+    IMM_TRY(dalloc(&p->hlist, slots * n));
+    IMM_TRY(dalloc(&p->hvisited, slots * p->vis_words));
+    HIP_TRY(hipMemset(p->hvisited, 0, sizeof(uint32_t) * (size_t)(slots * p->vis_words)));
+    p->hslots = slots;
+    return IMM_OK;
+}
+
+// Heavy launch over the queue the last light launch filled.
+static imm_status run_heavy(imm_pool* p, uint32_t n_queue, hipStream_t s) {
+    IMM_TRY(ensure_heavy(p));
+    HIP_TRY(hipMemsetAsync(&p->ctr->hwork, 0, sizeof(unsigned int), s));
+    GenArgs a = gen_args(p);
+    a.queue = p->heavy_list;
+    a.n_queue = n_queue;
+    a.first = 0;
+    a.count = n_queue;
+    a.list = p->heavy_list;
+    HIP_TRY(hipEventRecord(p->ev0, s));
+    if (p->model == IMM_IC) {
+        int64_t grid = std::min<int64_t>(p->hslots, n_queue);
+        HIP_TRY(launch_ic_heavy(a, p->heavy_block, (int)std::max<int64_t>(grid, 1), s));
+    } else {
+        // LT: sets too long for the on-chip list walk with their lists in HBM
+        HIP_TRY(hipMemsetAsync(&p->ctr->work, 0, sizeof(unsigned long long), s));
+        int64_t grid = std::min<int64_t>(p->hslots / 4, ((int64_t)n_queue + 3) / 4);
+        HIP_TRY(launch_lt(a, true, (int)std::max<int64_t>(grid, 1), s));
+    }
+    HIP_TRY(hipEventRecord(p->ev1, s));
+    IMM_TRY(read_counters(p, s));
+    p->heavy_s += elapsed_s(p);
+    p->heavy_launches += 1;
     return IMM_OK;
 }
 
@@ -539,61 +586,39 @@ static imm_status pool_generate(imm_pool* p, int64_t upto, hipStream_t s) {
     IMM_TRY(dgrow(&p->rr_len, &cap_sets, upto, p->count, s));
     p->cap_sets = cap_sets;
     if (cnt > p->cap_lists) {
-        dfree(p->ovf_list);
+        dfree(p->heavy_list);
         dfree(p->cap_list);
         dfree(p->retry_list);
-        int64_t c = cnt;
-        IMM_TRY(dalloc(&p->ovf_list, c));
-        IMM_TRY(dalloc(&p->cap_list, c));
-        IMM_TRY(dalloc(&p->retry_list, c));
-        p->cap_lists = c;
+        IMM_TRY(dalloc(&p->heavy_list, cnt));
+        IMM_TRY(dalloc(&p->cap_list, cnt));
+        IMM_TRY(dalloc(&p->retry_list, cnt));
+        p->cap_lists = cnt;
     }
-    // id-buffer size from the mean set size seen so far (x1.3, plus slack)
-    const double mean = p->count > 0 ? (double)p->host_ctr->placed / (double)p->count : 16.0;
-    const int64_t need = (int64_t)p->host_ctr->tail + (int64_t)(mean * 1.3 * (double)cnt) + 65536;
+    // id-buffer size from the mean set size seen so far, with room for the per-wave
+    // reservation chunks left partly unused at the end of each launch
+    const unsigned long long placed = sum64(p->host_ctr->placed);
+    const double mean = p->count > 0 ? (double)placed / (double)p->count : 16.0;
+    const int64_t slack = ((int64_t)p->grid * 4 + p->g->cus * 8) * (int64_t)2048;
+    const int64_t need = (int64_t)p->host_ctr->tail + (int64_t)(mean * 1.3 * (double)cnt) + slack;
     IMM_TRY(dgrow(&p->ids, &p->cap_ids, need, (int64_t)p->host_ctr->tail, s));
 
-    IMM_TRY(run_gen(p, false, first, cnt, nullptr, s));
+    IMM_TRY(run_light(p, first, cnt, nullptr, s));
     for (int guard = 0; guard < 64; ++guard) {
-        const unsigned int n_ovf = p->host_ctr->n_overflow;
-        const unsigned int n_cap0 = p->host_ctr->n_capacity;
-        if (n_ovf > 0) {
-            IMM_TRY(ensure_big(p));
-            // the capacity list keeps its entries: copy them aside before the big launch
-            // resets the counters
-            if (n_cap0 > 0)
-                HIP_TRY(hipMemcpyAsync(p->retry_list, p->cap_list, sizeof(uint32_t) * n_cap0,
-                                       hipMemcpyDeviceToDevice, s));
-            uint32_t* big_work = p->ovf_list;
-            // run the deferred sets from a copy so that the launch may append capacity misses
-            IMM_TRY(run_gen(p, true, 0, n_ovf, big_work, s));
-            const unsigned int n_cap1 = p->host_ctr->n_capacity;
-            if (n_cap0 > 0) {
-                // merge: retry = earlier misses + misses of the big launch
-                if (n_cap1 > 0)
-                    HIP_TRY(hipMemcpyAsync(p->retry_list + n_cap0, p->cap_list,
-                                           sizeof(uint32_t) * n_cap1, hipMemcpyDeviceToDevice, s));
-                HIP_TRY(hipMemcpyAsync(p->cap_list, p->retry_list,
-                                       sizeof(uint32_t) * (n_cap0 + n_cap1), hipMemcpyDeviceToDevice, s));
-                p->host_ctr->n_capacity = n_cap0 + n_cap1;
-            }
-            p->host_ctr->n_overflow = 0;
-        }
+        if (p->host_ctr->n_heavy > 0) IMM_TRY(run_heavy(p, p->host_ctr->n_heavy, s));
         const unsigned int n_cap = p->host_ctr->n_capacity;
-        if (n_cap == 0) break;
+        if (n_cap == 0) {
+            p->count = upto;
+            return IMM_OK;
+        }
         // grow the id buffer and rerun the sets that did not fit
         const int64_t tail = (int64_t)p->host_ctr->tail;
-        const double m2 = p->host_ctr->placed > 0 ? (double)p->host_ctr->placed / (double)(p->count + cnt) : mean;
-        const int64_t want = tail + (int64_t)(m2 * 2.0 * (double)n_cap) + (int64_t)p->g->n + 65536;
-        IMM_TRY(dgrow(&p->ids, &p->cap_ids, want > 2 * p->cap_ids ? want : 2 * p->cap_ids, tail, s));
+        const int64_t want = tail + (int64_t)(std::max(mean, 64.0) * 2.0 * (double)n_cap) + slack;
+        IMM_TRY(dgrow(&p->ids, &p->cap_ids, std::max(want, 2 * p->cap_ids), tail, s));
         HIP_TRY(hipMemcpyAsync(p->retry_list, p->cap_list, sizeof(uint32_t) * n_cap,
                                hipMemcpyDeviceToDevice, s));
-        IMM_TRY(run_gen(p, false, 0, n_cap, p->retry_list, s));
+        IMM_TRY(run_light(p, 0, n_cap, p->retry_list, s));
     }
-    if (p->host_ctr->n_capacity || p->host_ctr->n_overflow)
-        return fail(IMM_EDEVICE, "RR placement did not converge");
-    p->count = upto;
-    return IMM_OK;
+    return fail(IMM_EDEVICE, "RR placement did not converge");
 }
 
 extern "C" imm_status imm_generate_rr(imm_pool* p, int64_t upto, void* stream) {
@@ -684,7 +709,7 @@ static imm_status ensure_select(imm_pool* p, int64_t count, int32_t k) {
         IMM_TRY(dalloc(&p->cursor, n));
         IMM_TRY(dalloc(&p->n_covered, 1));
     }
-    const int64_t members = (int64_t)p->host_ctr->placed;
+    const int64_t members = (int64_t)sum64(p->host_ctr->placed);
     if (members > p->cap_inv) {
         dfree(p->inv);
         int64_t c = members + members / 4 + 1024;
@@ -757,8 +782,8 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
     if (!seeds_out) return fail(IMM_EINVAL, "seeds_out is NULL");
     const double t0 = now_s();
     double t_gen = 0.0, t_sel = 0.0;
-    const double kernel_s0 = p->kernel_s;
-    const int64_t launches0 = p->kernel_launches;
+    const double kernel_s0 = p->kernel_s, heavy_s0 = p->heavy_s;
+    const int64_t launches0 = p->kernel_launches, heavy0 = p->heavy_launches;
     const double lp = ell_prime(n, ell);
     const double ep = std::sqrt(2.0) * eps;
     const double lam1 = lambda_prime(n, k, eps, lp);
@@ -803,8 +828,9 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
         info->theta = theta;
         info->num_rr = upto;
         info->covered = cov;
-        info->edges_examined = (int64_t)p->host_ctr->edges;
-        info->pool_ids = (int64_t)p->host_ctr->placed;
+        info->edges_examined = (int64_t)(sum64(p->host_ctr->edges) + sum64(p->host_ctr->hedges));
+        info->edges_heavy = (int64_t)sum64(p->host_ctr->hedges);
+        info->pool_ids = (int64_t)sum64(p->host_ctr->placed);
         info->phases = phases;
         info->lb = lb;
         info->spread_est = (double)n * (double)cov / (double)(upto - first);
@@ -815,6 +841,8 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
         info->t_total_s = now_s() - t0;
         info->t_rr_kernel_s = p->kernel_s - kernel_s0;
         info->rr_kernel_launches = p->kernel_launches - launches0;
+        info->t_rr_heavy_s = p->heavy_s - heavy_s0;
+        info->rr_heavy_launches = p->heavy_launches - heavy0;
     }
     return IMM_OK;
 }

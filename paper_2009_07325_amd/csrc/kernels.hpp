@@ -8,15 +8,18 @@
 
 namespace imm {
 
-// Device-side counters of one pool (one 64-byte block, zeroed at pool creation).
+// Device-side counters of one pool (zeroed at pool creation).  Counters that every wave
+// updates once per launch are spread over 64 slots (index = wave slot & 63).
 struct alignas(64) PoolCounters {
-    unsigned long long tail;       // next free slot of the id buffer (reservations)
-    unsigned long long placed;     // members written (sum of sizes of placed sets)
-    unsigned long long edges;      // in-edges examined
-    unsigned long long work;       // work-queue cursor of the current launch
-    unsigned int n_overflow;       // sets deferred by the current launch
+    unsigned long long tail;       // next free entry of the id buffer (chunk reservations)
+    unsigned long long work;       // work-queue cursor of the current light launch
+    unsigned int hwork;            // work-queue cursor of the current heavy launch
+    unsigned int n_heavy;          // sets queued for the heavy kernel by the light launch
     unsigned int n_capacity;       // sets that found the id buffer full
-    unsigned int pad[6];
+    unsigned int pad[9];
+    unsigned long long placed[64]; // members written
+    unsigned long long edges[64];  // in-edges examined by sets placed by the light kernel
+    unsigned long long hedges[64]; // ... by the heavy kernel
 };
 
 // ---- graph.hip ----------------------------------------------------------------------
@@ -36,14 +39,19 @@ struct GenArgs {
     // graph
     const VRec* vrec;
     const int32_t* src;
-    const uint32_t* thr;     // IC per-edge thresholds (null when every vertex is uniform)
+    const uint32_t* thr;     // IC per-edge thresholds (padded to a multiple of 4 edges)
     const uint32_t* cum;     // LT cumulative thresholds
     int32_t n;
     uint32_t k0, k1;         // Philox key
-    // work: RR indices first + i for i in [0, count), or list[i] when list is set
+    // light launch: RR indices first + i for i in [0, count), or list[i] when list is set
     int64_t first;
     int64_t count;
     const uint32_t* list;
+    int64_t budget;          // 4-edge groups a light wave may examine for one set
+    uint32_t* heavy_list;    // light -> heavy queue
+    // heavy launch: queue[0 .. n_queue)
+    const uint32_t* queue;
+    uint32_t n_queue;
     // outputs
     int32_t* ids;
     int64_t cap_ids;
@@ -51,20 +59,21 @@ struct GenArgs {
     int32_t* rr_len;
     uint32_t* hist;
     PoolCounters* ctr;
-    uint32_t* ovf_list;      // deferred RR indices (too big for the on-chip list)
     uint32_t* cap_list;      // RR indices that found the id buffer full
     // scratch
-    uint32_t* visited;       // one n-bit bitmap per wave slot
+    uint32_t* visited;       // light: one n-bit bitmap per wave slot
+    uint32_t* hvisited;      // heavy: one n-bit bitmap per heavy slot
     int64_t vis_words;       // words per bitmap
-    int32_t* big_list;       // one n-entry member list per wave slot (big-set launch)
+    int32_t* hlist;          // heavy: one n-entry member list per heavy slot
 };
 
-// Launches the on-chip-list generator (sets larger than its list are deferred) or the
-// big-set generator (member lists in HBM).  `grid` blocks of 256 threads.
-hipError_t launch_rr_ic(const GenArgs& a, bool big, int grid, hipStream_t s);
-hipError_t launch_rr_lt(const GenArgs& a, bool big, int grid, hipStream_t s);
-int rr_small_capacity();           // members held on chip per set
-int rr_blocks_per_cu(bool lt, bool big);
+hipError_t launch_ic_light(const GenArgs& a, int grid, hipStream_t s);   // 256-thread blocks
+hipError_t launch_ic_heavy(const GenArgs& a, int block, int grid, hipStream_t s);  // 256 or 1024
+hipError_t launch_lt(const GenArgs& a, bool big, int grid, hipStream_t s);
+int rr_light_capacity();
+// occupancy in blocks per CU: 0 IC light, 1 IC heavy (1024), 2 LT, 3 LT with HBM lists,
+// 4 IC heavy (256)
+int gen_blocks_per_cu(int which);
 
 // Sorts each set's members ascending into the host-bound export buffer.
 hipError_t launch_gather_sets(const int64_t* rr_start, const int32_t* rr_len, int64_t first,

@@ -1,119 +1,172 @@
 // Random RR-set generation on gfx950.
 //
 // IC (gIM Sec. II-E, Alg. 3-6): RR set r is every vertex that reaches root(r) in the
-// live-edge instance drawn for r.  We enumerate it by a breadth-first search over in-edges
-// in which every in-edge of an expanded vertex is tested once against its own Philox draw,
-// and a visited test-and-set admits each vertex once (the duplicate-frontier hazard of gIM
-// Sec. III-A).  Because each edge's draw is keyed by (r, e), the set does not depend on the
-// order of expansion, so a whole wave can expand many frontier vertices at once.
+// live-edge instance drawn for r.  We enumerate it breadth-first over in-edges, testing
+// every in-edge of an expanded vertex once against its own Philox draw; a visited
+// test-and-set admits each vertex once (the duplicate-frontier hazard of gIM Sec. III-A).
+// Draws are keyed by (r, e), so the set does not depend on the order of expansion: a wave
+// expands up to 64 frontier vertices at once, their in-edges flattened into aligned 4-edge
+// groups, one Philox4x32-10 call per lane per group.
 //
 // LT (gIM Sec. III-G): RR set r is the reverse walk from root(r) in which each vertex picks
-// at most one in-edge (the first cumulative threshold above its draw) and the walk stops
-// at a vertex with no in-edge, no pick, or a pick already on the walk.
+// at most one in-edge (the first cumulative threshold above its draw); the walk stops at a
+// vertex with no in-edge, no pick, or a pick already on the walk.
 //
-// Launch shape (persistent, gIM Alg. 6 / Eq. 5 analogue): a grid sized to fill every CU;
-// each wave pulls RR indices from an atomic work counter until the range is exhausted.
-// Members of the current set live in an on-chip (LDS) list of kListCap entries; a set that
-// outgrows it is abandoned and deferred to the big-set launch, which keeps member lists in
-// HBM (the role of gIM's reservoir queue Q_res, Sec. III-C).  Finished sets are placed in
-// the pool's id buffer at an atomically reserved offset (gIM Alg. 6's tail_RR), and the
-// pool's occurrence counts are incremented for each member (gIM Sec. III-B, Occur).
+// Work split (the role of gIM's N_b persistent blocks, Alg. 6 / Eq. 5).  On skewed graphs
+// the in-edges examined per set span five orders of magnitude and ~1% of the sets carry
+// half of the work, so one set per block (the paper's choice) leaves the GPU waiting on a
+// few sets.  Two kernels:
+//   light : one wave per set, pulled 8 indices at a time from a work counter.  A set whose
+//           examined 4-edge groups would exceed a budget, or whose members outgrow the
+//           on-chip list, is abandoned and queued for the heavy kernel (its partial work is
+//           redone there; the budget bounds the waste).
+//   heavy : one workgroup (4 or 16 waves) per queued set, member list in HBM.
+// Finished sets are written into the pool's id buffer at offsets reserved per wave in
+// chunks (gIM Alg. 6's tail_RR, without a per-set atomic) and counted into the occurrence
+// histogram (gIM Sec. III-B, Occur).  Counters that every wave updates are spread over 64
+// addresses: device-scope atomics on one address serialise across the 8 XCDs.
 #include "kernels.hpp"
 
 namespace imm {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kListCap = 2048;
+constexpr int kLightCap = 1024;    // members a light set may hold on chip
+constexpr int kFetch = 8;          // RR indices per work-counter fetch
+constexpr int kIdChunk = 1024;     // id-buffer entries reserved per wave at a time
 
-int rr_small_capacity() { return kListCap; }
+int rr_light_capacity() { return kLightCap; }
 
-struct FrontierLds {
-    int32_t pre[kWave + 1];   // exclusive prefix of 4-edge group counts of the batch
-    int64_t start[kWave];     // first in-edge of each batch vertex
-    uint32_t deg[kWave];      // in-degree | uniform bit
-    uint32_t thr[kWave];      // common threshold when uniform
-};
-
-template <bool kBig>
-struct WaveLds {
-    FrontierLds f;
-    int32_t list[kBig ? 1 : kListCap];
-};
-
+// ------------------------------------------------------------------------------------
+// shared helpers
+// ------------------------------------------------------------------------------------
 __device__ __forceinline__ void vis_clear(uint32_t* vis, int32_t v) { vis[v >> 5] = 0u; }
 
 __device__ __forceinline__ bool vis_test_and_set(uint32_t* vis, int32_t v) {
     const uint32_t bit = 1u << (v & 31);
-    uint32_t old = __hip_atomic_fetch_or(vis + (v >> 5), bit, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t old = __hip_atomic_fetch_or(vis + (v >> 5), bit, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
     return (old & bit) == 0u;
 }
 
-// Pull the next RR index of this launch (uniform across the wave); false when done.
-__device__ __forceinline__ bool next_index(const GenArgs& a, uint32_t& r) {
-    unsigned long long i = 0;
-    if (lane_id() == 0) i = atomic_add_agent(&a.ctr->work, 1ull);
-    i = uniform64(i);
-    if ((int64_t)i >= a.count) return false;
-    r = a.list ? a.list[i] : (uint32_t)(a.first + (int64_t)i);
-    r = uniform(r);
+// Orders the visited-bitmap clears of one set before the next set's test-and-sets.
+__device__ __forceinline__ void vis_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
+__device__ __forceinline__ uint32_t set_index(const GenArgs& a, int64_t i) {
+    return a.list ? a.list[i] : (uint32_t)(a.first + i);
+}
+
+// Wave-private state kept in (uniform) registers.
+struct WaveState {
+    int64_t cur = 0, end = 0;                // fetched index range [cur, end)
+    unsigned long long chunk_base = 0;       // reserved id-buffer chunk
+    int64_t chunk_left = 0;
+    unsigned long long placed = 0, edges = 0;
+    uint32_t heavy_buf = 0;                  // lane i holds the i-th queued RR index
+    int heavy_n = 0;
+};
+
+__device__ __forceinline__ bool next_set(const GenArgs& a, WaveState& ws, uint32_t& r) {
+    if (ws.cur >= ws.end) {
+        unsigned long long i = 0;
+        if (lane_id() == 0) i = atomic_add_agent(&a.ctr->work, (unsigned long long)kFetch);
+        i = uniform64(i);
+        if ((int64_t)i >= a.count) return false;
+        ws.cur = (int64_t)i;
+        ws.end = min((int64_t)i + kFetch, a.count);
+    }
+    r = uniform(set_index(a, ws.cur));
+    ++ws.cur;
     return true;
 }
 
-// Place a finished set: reserve space, copy members, count occurrences.  Returns false
-// when the id buffer is full (the index is queued for a retry after the host grows it).
-__device__ bool place_set(const GenArgs& a, uint32_t r, const int32_t* list, int32_t size,
-                          uint64_t examined) {
+__device__ __forceinline__ void flush_heavy(const GenArgs& a, WaveState& ws) {
+    if (ws.heavy_n == 0) return;
+    unsigned int at = 0;
+    if (lane_id() == 0) at = atomic_add_agent(&a.ctr->n_heavy, (unsigned int)ws.heavy_n);
+    at = uniform(at);
+    if (lane_id() < ws.heavy_n) a.heavy_list[at + lane_id()] = ws.heavy_buf;
+    ws.heavy_n = 0;
+}
+
+__device__ __forceinline__ void push_heavy(const GenArgs& a, WaveState& ws, uint32_t r) {
+    if (lane_id() == ws.heavy_n) ws.heavy_buf = r;
+    if (++ws.heavy_n == kWave) flush_heavy(a, ws);
+}
+
+__device__ __forceinline__ void push_capacity_miss(const GenArgs& a, uint32_t r) {
+    const unsigned int at = atomic_add_agent(&a.ctr->n_capacity, 1u);
+    a.cap_list[at] = r;
+}
+
+// Write a finished set (members list[0..size)) into the id buffer; wave-cooperative.
+__device__ void place_wave(const GenArgs& a, WaveState& ws, uint32_t r, const int32_t* list,
+                           int32_t size, uint64_t examined) {
     const int lane = lane_id();
-    unsigned long long base = 0;
-    if (lane == 0) base = atomic_add_agent(&a.ctr->tail, (unsigned long long)size);
-    base = uniform64(base);
-    if ((int64_t)(base + (unsigned long long)size) > a.cap_ids) {
-        if (lane == 0) {
-            unsigned int at = atomic_add_agent(&a.ctr->n_capacity, 1u);
-            a.cap_list[at] = r;
+    if (ws.chunk_left < size) {
+        const int64_t want = max((int64_t)kIdChunk, (int64_t)size);
+        unsigned long long base = 0;
+        if (lane == 0) base = atomic_add_agent(&a.ctr->tail, (unsigned long long)want);
+        base = uniform64(base);
+        if ((int64_t)base + want > a.cap_ids) {
+            if (lane == 0) push_capacity_miss(a, r);
+            ws.chunk_left = 0;
+            return;
         }
-        return false;
+        ws.chunk_base = base;
+        ws.chunk_left = want;
     }
     for (int32_t i = lane; i < size; i += kWave) {
-        int32_t v = list[i];
-        a.ids[base + i] = v;
+        const int32_t v = list[i];
+        a.ids[ws.chunk_base + i] = v;
         __hip_atomic_fetch_add(a.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
-        a.rr_start[r] = (int64_t)base;
+        a.rr_start[r] = (int64_t)ws.chunk_base;
         a.rr_len[r] = size;
-        atomic_add_agent(&a.ctr->placed, (unsigned long long)size);
-        atomic_add_agent(&a.ctr->edges, (unsigned long long)examined);
     }
-    return true;
+    ws.chunk_base += (unsigned long long)size;
+    ws.chunk_left -= size;
+    ws.placed += (unsigned long long)size;
+    ws.edges += examined;
 }
 
-__device__ __forceinline__ void defer_overflow(const GenArgs& a, uint32_t r) {
+__device__ __forceinline__ void wave_exit(const GenArgs& a, WaveState& ws, int64_t slot) {
+    flush_heavy(a, ws);
     if (lane_id() == 0) {
-        unsigned int at = atomic_add_agent(&a.ctr->n_overflow, 1u);
-        a.ovf_list[at] = r;
+        if (ws.placed) atomic_add_agent(&a.ctr->placed[slot & 63], ws.placed);
+        if (ws.edges) atomic_add_agent(&a.ctr->edges[slot & 63], ws.edges);
     }
 }
 
 // ------------------------------------------------------------------------------------
-// IC
+// IC light kernel: one wave per set.
 // ------------------------------------------------------------------------------------
-template <bool kBig>
-__global__ __launch_bounds__(kBlock) void k_rr_ic(GenArgs a) {
-    __shared__ WaveLds<kBig> lds_all[kWavesPerBlock];
+struct FrontierLds {
+    int32_t pre[kWave + 1];   // exclusive prefix of 4-edge group counts of the batch
+    uint32_t start[kWave];    // first in-edge of each batch vertex
+    uint32_t deg[kWave];      // in-degree | uniform bit
+    uint32_t thr[kWave];      // common threshold when uniform
+};
+
+struct LightLds {
+    FrontierLds f;
+    int32_t list[kLightCap];
+};
+
+__global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
+    __shared__ LightLds lds_all[kWavesPerBlock];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
-    WaveLds<kBig>& L = lds_all[wib];
+    LightLds& L = lds_all[wib];
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
     uint32_t* vis = a.visited + slot * a.vis_words;
-    int32_t* list = kBig ? a.big_list + slot * (int64_t)a.n : L.list;
-    const int32_t cap = kBig ? a.n : kListCap;
+    int32_t* list = L.list;
     const uint32_t k0 = a.k0, k1 = a.k1;
+    WaveState ws;
 
     uint32_t r;
-    while (next_index(a, r)) {
+    while (next_set(a, ws, r)) {
         const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
         if (lane == 0) {
             list[0] = root;
@@ -121,20 +174,21 @@ __global__ __launch_bounds__(kBlock) void k_rr_ic(GenArgs a) {
         }
         int32_t size = 1, head = 0;
         uint64_t examined = 0;
-        bool overflow = false;
-        if (kBig) __threadfence(); else wave_sync();
+        int64_t used = 0;
+        bool abandon = false;
+        wave_sync();
 
-        while (head < size && !overflow) {
+        while (head < size && !abandon) {
             const int32_t nb = min(size - head, kWave);
-            // -- batch of up to 64 frontier vertices: their in-edge groups, flattened --
             int32_t ng = 0;
             uint32_t dg = 0;
             if (lane < nb) {
                 const int32_t v = list[head + lane];
                 const VRec rec = a.vrec[v];
                 dg = rec.deg & kDegMask;
-                if (dg) ng = (int32_t)(((rec.start + dg - 1) >> 2) - (rec.start >> 2) + 1);
-                L.f.start[lane] = rec.start;
+                const uint32_t st = (uint32_t)rec.start;
+                if (dg) ng = (int32_t)(((st + dg - 1) >> 2) - (st >> 2) + 1);
+                L.f.start[lane] = st;
                 L.f.deg[lane] = rec.deg;
                 L.f.thr[lane] = rec.thr;
             }
@@ -144,8 +198,13 @@ __global__ __launch_bounds__(kBlock) void k_rr_ic(GenArgs a) {
             const int32_t total = __shfl(incl, nb - 1, kWave);
             examined += (uint64_t)wave_sum((uint64_t)dg);
             wave_sync();
+            if (used + total > a.budget) {
+                abandon = true;
+                break;
+            }
+            used += total;
 
-            for (int32_t base = 0; base < total && !overflow; base += kWave) {
+            for (int32_t base = 0; base < total && !abandon; base += kWave) {
                 const int32_t q = base + lane;
                 int32_t w[4] = {0, 0, 0, 0};
                 bool fresh[4] = {false, false, false, false};
@@ -155,23 +214,22 @@ __global__ __launch_bounds__(kBlock) void k_rr_ic(GenArgs a) {
                         const int32_t mid = (lo + hi) >> 1;
                         if (L.f.pre[mid] <= q) lo = mid; else hi = mid;
                     }
-                    const int64_t s = L.f.start[lo];
+                    const uint32_t s = L.f.start[lo];
                     const uint32_t dd = L.f.deg[lo];
-                    const int64_t e_end = s + (dd & kDegMask);
-                    const uint32_t g = (uint32_t)((s >> 2) + (q - L.f.pre[lo]));
-                    const int64_t e0 = (int64_t)g << 2;
+                    const uint32_t e_end = s + (dd & kDegMask);
+                    const uint32_t g = (s >> 2) + (uint32_t)(q - L.f.pre[lo]);
                     const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, k0, k1);
                     uint32_t t[4];
                     if (dd & kUniformBit) {
                         t[0] = t[1] = t[2] = t[3] = L.f.thr[lo];
                     } else {
-                        const uint4 tv = *reinterpret_cast<const uint4*>(a.thr + e0);
+                        const uint4 tv = *reinterpret_cast<const uint4*>(a.thr + ((int64_t)g << 2));
                         t[0] = tv.x; t[1] = tv.y; t[2] = tv.z; t[3] = tv.w;
                     }
                     const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int64_t e = e0 + j;
+                        const uint32_t e = (g << 2) + j;
                         const bool live = e >= s && e < e_end && (t[j] == kAlways || xs[j] < t[j]);
                         if (live) {
                             w[j] = a.src[e];
@@ -179,38 +237,194 @@ __global__ __launch_bounds__(kBlock) void k_rr_ic(GenArgs a) {
                         }
                     }
                 }
-                // -- append the newly reached vertices (ballot + prefix count) --
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint64_t mask = ballot(fresh[j]);
                     const int32_t cnt = (int32_t)__popcll(mask);
                     if (cnt == 0) continue;
-                    if (overflow || size + cnt > cap) {
-                        overflow = true;
+                    if (abandon || size + cnt > kLightCap) {
+                        abandon = true;
                         if (fresh[j]) vis_clear(vis, w[j]);
                         continue;
                     }
                     if (fresh[j]) list[size + (int32_t)lanes_below(mask)] = w[j];
                     size += cnt;
                 }
-                if (kBig) __threadfence(); else wave_sync();
+                wave_sync();
             }
             head += nb;
         }
-
-        bool placed = false;
-        if (!overflow) placed = place_set(a, r, list, size, examined);
-        else defer_overflow(a, r);
-        (void)placed;
+        if (abandon) push_heavy(a, ws, r);
+        else place_wave(a, ws, r, list, size, examined);
         for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
-        __threadfence();
+        vis_fence();
+        wave_sync();
+    }
+    wave_exit(a, ws, slot);
+}
+
+// ------------------------------------------------------------------------------------
+// IC heavy kernel: one 1024-thread workgroup per set, member list in HBM.
+// ------------------------------------------------------------------------------------
+// Inclusive block scan of one int per thread (up to 1024 threads).
+template <int kHeavyBlock>
+__device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* wsum) {
+    constexpr int kHeavyWaves = kHeavyBlock / kWave;
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    int32_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        int32_t t = lane < kHeavyWaves ? wsum[lane] : 0;
+        int32_t ti = wave_incl_scan(t);
+        if (lane < kHeavyWaves) wsum[lane] = ti - t;
+    }
+    __syncthreads();
+    incl += wsum[wid];
+    __syncthreads();
+    return incl;
+}
+
+template <int kHeavyBlock>
+__global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
+    constexpr int kHeavyWaves = kHeavyBlock / kWave;
+    __shared__ int32_t pre[kHeavyBlock + 1];
+    __shared__ uint32_t st[kHeavyBlock], dgs[kHeavyBlock], ths[kHeavyBlock];
+    __shared__ int32_t wsum[kHeavyWaves];
+    __shared__ unsigned long long wred[kHeavyWaves];
+    __shared__ int32_t s_size;
+    __shared__ unsigned int s_idx;
+    __shared__ unsigned long long s_base;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const int64_t slot = blockIdx.x;
+    uint32_t* vis = a.hvisited + slot * a.vis_words;
+    int32_t* list = a.hlist + slot * (int64_t)a.n;
+    const uint32_t k0 = a.k0, k1 = a.k1;
+    unsigned long long placed = 0, edges = 0;
+
+    for (;;) {
+        if (tid == 0) s_idx = atomic_add_agent(&a.ctr->hwork, 1u);
+        __syncthreads();
+        const unsigned int idx = s_idx;
+        if (idx >= a.n_queue) break;
+        const uint32_t r = a.queue[idx];
+        if (tid == 0) {
+            const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
+            list[0] = root;
+            vis_test_and_set(vis, root);
+            s_size = 1;
+        }
+        __syncthreads();
+        int32_t head = 0, size = s_size;
+        unsigned long long examined = 0;
+        while (head < size) {
+            const int32_t nb = min(size - head, kHeavyBlock);
+            int32_t ng = 0;
+            uint32_t dg = 0;
+            if (tid < nb) {
+                const VRec rec = a.vrec[list[head + tid]];
+                dg = rec.deg & kDegMask;
+                const uint32_t s0 = (uint32_t)rec.start;
+                if (dg) ng = (int32_t)(((s0 + dg - 1) >> 2) - (s0 >> 2) + 1);
+                st[tid] = s0;
+                dgs[tid] = rec.deg;
+                ths[tid] = rec.thr;
+            }
+            const unsigned long long dsum = wave_sum((unsigned long long)dg);
+            if (lane == 0) wred[wid] = dsum;
+            const int32_t incl = block_incl_scan<kHeavyBlock>(ng, wsum);
+            if (tid < nb) pre[tid] = incl - ng;
+            if (tid == nb - 1) pre[nb] = incl;
+            __syncthreads();
+            if (tid == 0)
+                for (int w = 0; w < kHeavyWaves; ++w) examined += wred[w];
+            const int32_t total = pre[nb];
+            for (int32_t base = 0; base < total; base += kHeavyBlock) {
+                const int32_t q = base + tid;
+                int32_t w[4] = {0, 0, 0, 0};
+                bool fresh[4] = {false, false, false, false};
+                if (q < total) {
+                    int32_t lo = 0, hi = nb;
+                    while (hi - lo > 1) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (pre[mid] <= q) lo = mid; else hi = mid;
+                    }
+                    const uint32_t s0 = st[lo];
+                    const uint32_t dd = dgs[lo];
+                    const uint32_t e_end = s0 + (dd & kDegMask);
+                    const uint32_t g = (s0 >> 2) + (uint32_t)(q - pre[lo]);
+                    const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, k0, k1);
+                    uint32_t t[4];
+                    if (dd & kUniformBit) {
+                        t[0] = t[1] = t[2] = t[3] = ths[lo];
+                    } else {
+                        const uint4 tv = *reinterpret_cast<const uint4*>(a.thr + ((int64_t)g << 2));
+                        t[0] = tv.x; t[1] = tv.y; t[2] = tv.z; t[3] = tv.w;
+                    }
+                    const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t e = (g << 2) + j;
+                        const bool live = e >= s0 && e < e_end && (t[j] == kAlways || xs[j] < t[j]);
+                        if (live) {
+                            w[j] = a.src[e];
+                            fresh[j] = vis_test_and_set(vis, w[j]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint64_t mask = ballot(fresh[j]);
+                    const int32_t cnt = (int32_t)__popcll(mask);
+                    if (cnt == 0) continue;
+                    int32_t at = 0;
+                    if (lane == 0) at = atomicAdd(&s_size, cnt);
+                    at = __shfl(at, 0, kWave);
+                    if (fresh[j]) list[at + (int32_t)lanes_below(mask)] = w[j];
+                }
+            }
+            __syncthreads();
+            head += nb;
+            size = s_size;
+            __syncthreads();
+        }
+        // place the set
+        if (tid == 0) {
+            unsigned long long b = atomic_add_agent(&a.ctr->tail, (unsigned long long)size);
+            if ((int64_t)b + size > a.cap_ids) {
+                push_capacity_miss(a, r);
+                b = ~0ull;
+            } else {
+                a.rr_start[r] = (int64_t)b;
+                a.rr_len[r] = size;
+                placed += (unsigned long long)size;
+                edges += examined;
+            }
+            s_base = b;
+        }
+        __syncthreads();
+        const unsigned long long b = s_base;
+        for (int32_t i = tid; i < size; i += kHeavyBlock) {
+            const int32_t v = list[i];
+            if (b != ~0ull) {
+                a.ids[b + i] = v;
+                __hip_atomic_fetch_add(a.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            vis_clear(vis, v);
+        }
+        vis_fence();
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (placed) atomic_add_agent(&a.ctr->placed[slot & 63], placed);
+        if (edges) atomic_add_agent(&a.ctr->hedges[slot & 63], edges);
     }
 }
 
 // ------------------------------------------------------------------------------------
-// LT: reverse walk.  The wave finds the chosen in-edge of the current vertex: for short
-// in-lists one coalesced load and a ballot; for long ones a 64-ary search over the
-// non-decreasing cumulative thresholds.
+// LT: reverse walk, one wave per set.  The wave finds the chosen in-edge of the current
+// vertex: for short in-lists one coalesced load and a ballot; for long ones a 64-ary
+// search over the non-decreasing cumulative thresholds.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ bool lt_hit(const GenArgs& a, int64_t j, uint32_t x) {
     const uint32_t c = a.cum[j];
@@ -247,18 +461,18 @@ __device__ __forceinline__ int64_t lt_pick(const GenArgs& a, int64_t s, int64_t 
 
 template <bool kBig>
 __global__ __launch_bounds__(kBlock) void k_rr_lt(GenArgs a) {
-    __shared__ WaveLds<kBig> lds_all[kWavesPerBlock];
+    __shared__ int32_t lds_list[kWavesPerBlock][kBig ? 1 : kLightCap];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
-    WaveLds<kBig>& L = lds_all[wib];
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
-    uint32_t* vis = a.visited + slot * a.vis_words;
-    int32_t* list = kBig ? a.big_list + slot * (int64_t)a.n : L.list;
-    const int32_t cap = kBig ? a.n : kListCap;
+    uint32_t* vis = (kBig ? a.hvisited : a.visited) + slot * a.vis_words;
+    int32_t* list = kBig ? a.hlist + slot * (int64_t)a.n : lds_list[wib];
+    const int32_t cap = kBig ? a.n : kLightCap;
     const uint32_t k0 = a.k0, k1 = a.k1;
+    WaveState ws;
 
     uint32_t r;
-    while (next_index(a, r)) {
+    while (next_set(a, ws, r)) {
         int32_t v = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
         if (lane == 0) {
             list[0] = v;
@@ -266,8 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenArgs a) {
         }
         int32_t size = 1;
         uint64_t examined = 0;
-        bool overflow = false;
-        if (kBig) __threadfence(); else wave_sync();
+        bool abandon = false;
         for (;;) {
             const VRec rec = a.vrec[v];
             const uint32_t d = rec.deg & kDegMask;
@@ -282,42 +495,54 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenArgs a) {
             fresh = __shfl(fresh, 0, kWave);
             if (!fresh) break;
             if (size + 1 > cap) {
-                overflow = true;
+                abandon = true;
                 if (lane == 0) vis_clear(vis, u);
                 break;
             }
             if (lane == 0) list[size] = u;
             ++size;
             v = u;
-            if (kBig) __threadfence(); else wave_sync();
         }
         if (kBig) __threadfence(); else wave_sync();
-        if (!overflow) place_set(a, r, list, size, examined);
-        else defer_overflow(a, r);
+        if (abandon) push_heavy(a, ws, r);
+        else place_wave(a, ws, r, list, size, examined);
         for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
-        __threadfence();
+        vis_fence();
+        wave_sync();
     }
+    wave_exit(a, ws, slot);
 }
 
-hipError_t launch_rr_ic(const GenArgs& a, bool big, int grid, hipStream_t s) {
-    if (big) k_rr_ic<true><<<grid, kBlock, 0, s>>>(a);
-    else k_rr_ic<false><<<grid, kBlock, 0, s>>>(a);
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+hipError_t launch_ic_light(const GenArgs& a, int grid, hipStream_t s) {
+    k_ic_light<<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_rr_lt(const GenArgs& a, bool big, int grid, hipStream_t s) {
+hipError_t launch_ic_heavy(const GenArgs& a, int block, int grid, hipStream_t s) {
+    if (block == 256) k_ic_heavy<256><<<grid, 256, 0, s>>>(a);
+    else k_ic_heavy<1024><<<grid, 1024, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lt(const GenArgs& a, bool big, int grid, hipStream_t s) {
     if (big) k_rr_lt<true><<<grid, kBlock, 0, s>>>(a);
     else k_rr_lt<false><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
-int rr_blocks_per_cu(bool lt, bool big) {
+int gen_blocks_per_cu(int which) {
     int nb = 0;
-    hipError_t e;
-    if (lt) e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<true>, kBlock, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<false>, kBlock, 0);
-    else e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_ic<true>, kBlock, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_ic<false>, kBlock, 0);
+    hipError_t e = hipSuccess;
+    switch (which) {
+        case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_light, kBlock, 0); break;
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<1024>, 1024, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<256>, 256, 0); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<false>, kBlock, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<true>, kBlock, 0); break;
+    }
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
