@@ -140,10 +140,82 @@ __device__ __forceinline__ void wave_exit(const GenArgs& a, WaveState& ws, int64
 }
 
 // ------------------------------------------------------------------------------------
+// IC: testing one 4-edge group and appending newly reached vertices
+// ------------------------------------------------------------------------------------
+// Vertices with at least this many 4-edge groups are expanded one at a time (all lanes on
+// consecutive groups of that vertex, no lane -> vertex search); smaller ones are packed
+// together and each lane finds its vertex by a search over the batch's group prefix.
+constexpr int32_t kBigGroups = 48;
+
+// Tests the in-edges of group g that lie in [s, e_end) for set r.  Live edges whose source
+// is newly visited are returned in w[] with fresh[] set.
+__device__ __forceinline__ void test_group(const GenArgs& a, uint32_t r, uint32_t g, uint32_t s,
+                                           uint32_t e_end, bool uniform_thr, uint32_t uthr,
+                                           uint32_t* vis, int32_t w[4], bool fresh[4]) {
+    const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, a.k0, a.k1);
+    uint32_t t[4];
+    if (uniform_thr) {
+        t[0] = t[1] = t[2] = t[3] = uthr;
+    } else {
+        const uint4 tv = *reinterpret_cast<const uint4*>(a.thr + ((int64_t)g << 2));
+        t[0] = tv.x; t[1] = tv.y; t[2] = tv.z; t[3] = tv.w;
+    }
+    const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t e = (g << 2) + j;
+        const bool live = e >= s && e < e_end && (t[j] == kAlways || xs[j] < t[j]);
+        if (live) {
+            w[j] = a.src[e];
+            fresh[j] = vis_test_and_set(vis, w[j]);
+        }
+    }
+}
+
+// Wave-level append into an on-chip list of capacity `cap`; on overflow the set is
+// abandoned (and the bits of the vertices not appended are cleared).
+__device__ __forceinline__ void append_wave(int32_t* list, int32_t& size, int32_t cap,
+                                            bool& abandon, uint32_t* vis, const int32_t w[4],
+                                            const bool fresh[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint64_t mask = ballot(fresh[j]);
+        const int32_t cnt = (int32_t)__popcll(mask);
+        if (cnt == 0) continue;
+        if (abandon || size + cnt > cap) {
+            abandon = true;
+            if (fresh[j]) vis_clear(vis, w[j]);
+            continue;
+        }
+        if (fresh[j]) list[size + (int32_t)lanes_below(mask)] = w[j];
+        size += cnt;
+    }
+}
+
+// Workgroup-level append into an HBM list (positions from an LDS counter).
+__device__ __forceinline__ void append_block(int32_t* list, int32_t* s_size, const int32_t w[4],
+                                             const bool fresh[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint64_t mask = ballot(fresh[j]);
+        const int32_t cnt = (int32_t)__popcll(mask);
+        if (cnt == 0) continue;
+        int32_t at = 0;
+        if (lane_id() == 0) at = atomicAdd(s_size, cnt);
+        at = __shfl(at, 0, kWave);
+        if (fresh[j]) list[at + (int32_t)lanes_below(mask)] = w[j];
+    }
+}
+
+__device__ __forceinline__ uint32_t groups_of(uint32_t start, uint32_t deg) {
+    return deg ? ((start + deg - 1) >> 2) - (start >> 2) + 1 : 0u;
+}
+
+// ------------------------------------------------------------------------------------
 // IC light kernel: one wave per set.
 // ------------------------------------------------------------------------------------
 struct FrontierLds {
-    int32_t pre[kWave + 1];   // exclusive prefix of 4-edge group counts of the batch
+    int32_t pre[kWave + 1];   // exclusive prefix of the small vertices' group counts
     uint32_t start[kWave];    // first in-edge of each batch vertex
     uint32_t deg[kWave];      // in-degree | uniform bit
     uint32_t thr[kWave];      // common threshold when uniform
@@ -162,12 +234,11 @@ __global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
     uint32_t* vis = a.visited + slot * a.vis_words;
     int32_t* list = L.list;
-    const uint32_t k0 = a.k0, k1 = a.k1;
     WaveState ws;
 
     uint32_t r;
     while (next_set(a, ws, r)) {
-        const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
+        const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, a.k0, a.k1);
         if (lane == 0) {
             list[0] = root;
             vis_test_and_set(vis, root);
@@ -180,23 +251,28 @@ __global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
 
         while (head < size && !abandon) {
             const int32_t nb = min(size - head, kWave);
-            int32_t ng = 0;
-            uint32_t dg = 0;
+            uint32_t ng = 0, dg = 0, st = 0, dgf = 0, th = 0;
             if (lane < nb) {
-                const int32_t v = list[head + lane];
-                const VRec rec = a.vrec[v];
-                dg = rec.deg & kDegMask;
-                const uint32_t st = (uint32_t)rec.start;
-                if (dg) ng = (int32_t)(((st + dg - 1) >> 2) - (st >> 2) + 1);
-                L.f.start[lane] = st;
-                L.f.deg[lane] = rec.deg;
-                L.f.thr[lane] = rec.thr;
+                const VRec rec = a.vrec[list[head + lane]];
+                dgf = rec.deg;
+                th = rec.thr;
+                dg = dgf & kDegMask;
+                st = (uint32_t)rec.start;
+                ng = groups_of(st, dg);
             }
-            const int32_t incl = wave_incl_scan(ng);
-            if (lane < nb) L.f.pre[lane] = incl - ng;
+            const bool big = ng >= (uint32_t)kBigGroups;
+            const int32_t ngs = big ? 0 : (int32_t)ng;
+            const int32_t incl = wave_incl_scan(ngs);
+            if (lane < nb) {
+                L.f.pre[lane] = incl - ngs;
+                L.f.start[lane] = st;
+                L.f.deg[lane] = dgf;
+                L.f.thr[lane] = th;
+            }
             if (lane == nb - 1) L.f.pre[nb] = incl;
-            const int32_t total = __shfl(incl, nb - 1, kWave);
-            examined += (uint64_t)wave_sum((uint64_t)dg);
+            const int32_t total_small = __shfl(incl, nb - 1, kWave);
+            const int64_t total = (int64_t)wave_sum((uint64_t)ng);
+            examined += wave_sum((uint64_t)dg);
             wave_sync();
             if (used + total > a.budget) {
                 abandon = true;
@@ -204,54 +280,47 @@ __global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
             }
             used += total;
 
-            for (int32_t base = 0; base < total && !abandon; base += kWave) {
+            // big vertices: one at a time, wave-uniform vertex data
+            uint64_t bigmask = ballot(big);
+            while (bigmask && !abandon) {
+                const int b = __ffsll((unsigned long long)bigmask) - 1;
+                bigmask &= bigmask - 1;
+                const uint32_t s0 = __builtin_amdgcn_readlane(st, b);
+                const uint32_t df = __builtin_amdgcn_readlane(dgf, b);
+                const uint32_t t0 = __builtin_amdgcn_readlane(th, b);
+                const uint32_t gb = __builtin_amdgcn_readlane(ng, b);
+                const uint32_t e_end = s0 + (df & kDegMask);
+                const uint32_t g0 = s0 >> 2;
+                for (uint32_t base = 0; base < gb && !abandon; base += kWave) {
+                    int32_t w[4] = {0, 0, 0, 0};
+                    bool fresh[4] = {false, false, false, false};
+                    if (base + lane < gb)
+                        test_group(a, r, g0 + base + lane, s0, e_end, (df & kUniformBit) != 0, t0,
+                                   vis, w, fresh);
+                    append_wave(list, size, kLightCap, abandon, vis, w, fresh);
+                }
+            }
+            wave_sync();
+
+            // small vertices: packed, each lane searches for its vertex
+            for (int32_t base = 0; base < total_small && !abandon; base += kWave) {
                 const int32_t q = base + lane;
                 int32_t w[4] = {0, 0, 0, 0};
                 bool fresh[4] = {false, false, false, false};
-                if (q < total) {
+                if (q < total_small) {
                     int32_t lo = 0, hi = nb;   // pre[lo] <= q < pre[hi]
                     while (hi - lo > 1) {
                         const int32_t mid = (lo + hi) >> 1;
                         if (L.f.pre[mid] <= q) lo = mid; else hi = mid;
                     }
-                    const uint32_t s = L.f.start[lo];
+                    const uint32_t s0 = L.f.start[lo];
                     const uint32_t dd = L.f.deg[lo];
-                    const uint32_t e_end = s + (dd & kDegMask);
-                    const uint32_t g = (s >> 2) + (uint32_t)(q - L.f.pre[lo]);
-                    const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, k0, k1);
-                    uint32_t t[4];
-                    if (dd & kUniformBit) {
-                        t[0] = t[1] = t[2] = t[3] = L.f.thr[lo];
-                    } else {
-                        const uint4 tv = *reinterpret_cast<const uint4*>(a.thr + ((int64_t)g << 2));
-                        t[0] = tv.x; t[1] = tv.y; t[2] = tv.z; t[3] = tv.w;
-                    }
-                    const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint32_t e = (g << 2) + j;
-                        const bool live = e >= s && e < e_end && (t[j] == kAlways || xs[j] < t[j]);
-                        if (live) {
-                            w[j] = a.src[e];
-                            fresh[j] = vis_test_and_set(vis, w[j]);
-                        }
-                    }
+                    test_group(a, r, (s0 >> 2) + (uint32_t)(q - L.f.pre[lo]), s0, s0 + (dd & kDegMask),
+                               (dd & kUniformBit) != 0, L.f.thr[lo], vis, w, fresh);
                 }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint64_t mask = ballot(fresh[j]);
-                    const int32_t cnt = (int32_t)__popcll(mask);
-                    if (cnt == 0) continue;
-                    if (abandon || size + cnt > kLightCap) {
-                        abandon = true;
-                        if (fresh[j]) vis_clear(vis, w[j]);
-                        continue;
-                    }
-                    if (fresh[j]) list[size + (int32_t)lanes_below(mask)] = w[j];
-                    size += cnt;
-                }
-                wave_sync();
+                append_wave(list, size, kLightCap, abandon, vis, w, fresh);
             }
+            wave_sync();
             head += nb;
         }
         if (abandon) push_heavy(a, ws, r);
@@ -264,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
 }
 
 // ------------------------------------------------------------------------------------
-// IC heavy kernel: one 1024-thread workgroup per set, member list in HBM.
+// IC heavy kernel: one workgroup per set, member list in HBM.
 // ------------------------------------------------------------------------------------
 // Inclusive block scan of one int per thread (up to 1024 threads).
 template <int kHeavyBlock>
@@ -288,18 +357,19 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* wsum) {
 template <int kHeavyBlock>
 __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
     constexpr int kHeavyWaves = kHeavyBlock / kWave;
+    constexpr uint32_t kBigHeavy = kHeavyBlock / 4;
     __shared__ int32_t pre[kHeavyBlock + 1];
     __shared__ uint32_t st[kHeavyBlock], dgs[kHeavyBlock], ths[kHeavyBlock];
+    __shared__ uint32_t bst[kHeavyBlock], bdg[kHeavyBlock], bth[kHeavyBlock], bng[kHeavyBlock];
     __shared__ int32_t wsum[kHeavyWaves];
     __shared__ unsigned long long wred[kHeavyWaves];
-    __shared__ int32_t s_size;
+    __shared__ int32_t s_size, s_nbig;
     __shared__ unsigned int s_idx;
     __shared__ unsigned long long s_base;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int64_t slot = blockIdx.x;
     uint32_t* vis = a.hvisited + slot * a.vis_words;
     int32_t* list = a.hlist + slot * (int64_t)a.n;
-    const uint32_t k0 = a.k0, k1 = a.k1;
     unsigned long long placed = 0, edges = 0;
 
     for (;;) {
@@ -309,7 +379,7 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
         if (idx >= a.n_queue) break;
         const uint32_t r = a.queue[idx];
         if (tid == 0) {
-            const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
+            const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, a.k0, a.k1);
             list[0] = root;
             vis_test_and_set(vis, root);
             s_size = 1;
@@ -319,25 +389,53 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
         unsigned long long examined = 0;
         while (head < size) {
             const int32_t nb = min(size - head, kHeavyBlock);
-            int32_t ng = 0;
-            uint32_t dg = 0;
+            if (tid == 0) s_nbig = 0;
+            uint32_t ng = 0, dg = 0, s0 = 0, dgf = 0, t0 = 0;
             if (tid < nb) {
                 const VRec rec = a.vrec[list[head + tid]];
-                dg = rec.deg & kDegMask;
-                const uint32_t s0 = (uint32_t)rec.start;
-                if (dg) ng = (int32_t)(((s0 + dg - 1) >> 2) - (s0 >> 2) + 1);
-                st[tid] = s0;
-                dgs[tid] = rec.deg;
-                ths[tid] = rec.thr;
+                dgf = rec.deg;
+                t0 = rec.thr;
+                dg = dgf & kDegMask;
+                s0 = (uint32_t)rec.start;
+                ng = groups_of(s0, dg);
             }
+            const bool big = ng >= kBigHeavy;
+            const int32_t ngs = big ? 0 : (int32_t)ng;
             const unsigned long long dsum = wave_sum((unsigned long long)dg);
             if (lane == 0) wred[wid] = dsum;
-            const int32_t incl = block_incl_scan<kHeavyBlock>(ng, wsum);
-            if (tid < nb) pre[tid] = incl - ng;
+            const int32_t incl = block_incl_scan<kHeavyBlock>(ngs, wsum);   // has barriers
+            if (tid < nb) {
+                pre[tid] = incl - ngs;
+                st[tid] = s0;
+                dgs[tid] = dgf;
+                ths[tid] = t0;
+                if (big) {
+                    const int32_t k = atomicAdd(&s_nbig, 1);
+                    bst[k] = s0;
+                    bdg[k] = dgf;
+                    bth[k] = t0;
+                    bng[k] = ng;
+                }
+            }
             if (tid == nb - 1) pre[nb] = incl;
             __syncthreads();
             if (tid == 0)
                 for (int w = 0; w < kHeavyWaves; ++w) examined += wred[w];
+            const int32_t nbig = s_nbig;
+            // big vertices: all threads on consecutive groups of one vertex
+            for (int32_t i = 0; i < nbig; ++i) {
+                const uint32_t bs = bst[i], bd = bdg[i], bt = bth[i], gb = bng[i];
+                const uint32_t e_end = bs + (bd & kDegMask), g0 = bs >> 2;
+                for (uint32_t base = 0; base < gb; base += kHeavyBlock) {
+                    int32_t w[4] = {0, 0, 0, 0};
+                    bool fresh[4] = {false, false, false, false};
+                    if (base + tid < gb)
+                        test_group(a, r, g0 + base + tid, bs, e_end, (bd & kUniformBit) != 0, bt, vis,
+                                   w, fresh);
+                    append_block(list, &s_size, w, fresh);
+                }
+            }
+            // small vertices, packed
             const int32_t total = pre[nb];
             for (int32_t base = 0; base < total; base += kHeavyBlock) {
                 const int32_t q = base + tid;
@@ -349,39 +447,12 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
                         const int32_t mid = (lo + hi) >> 1;
                         if (pre[mid] <= q) lo = mid; else hi = mid;
                     }
-                    const uint32_t s0 = st[lo];
+                    const uint32_t ss = st[lo];
                     const uint32_t dd = dgs[lo];
-                    const uint32_t e_end = s0 + (dd & kDegMask);
-                    const uint32_t g = (s0 >> 2) + (uint32_t)(q - pre[lo]);
-                    const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, k0, k1);
-                    uint32_t t[4];
-                    if (dd & kUniformBit) {
-                        t[0] = t[1] = t[2] = t[3] = ths[lo];
-                    } else {
-                        const uint4 tv = *reinterpret_cast<const uint4*>(a.thr + ((int64_t)g << 2));
-                        t[0] = tv.x; t[1] = tv.y; t[2] = tv.z; t[3] = tv.w;
-                    }
-                    const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint32_t e = (g << 2) + j;
-                        const bool live = e >= s0 && e < e_end && (t[j] == kAlways || xs[j] < t[j]);
-                        if (live) {
-                            w[j] = a.src[e];
-                            fresh[j] = vis_test_and_set(vis, w[j]);
-                        }
-                    }
+                    test_group(a, r, (ss >> 2) + (uint32_t)(q - pre[lo]), ss, ss + (dd & kDegMask),
+                               (dd & kUniformBit) != 0, ths[lo], vis, w, fresh);
                 }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint64_t mask = ballot(fresh[j]);
-                    const int32_t cnt = (int32_t)__popcll(mask);
-                    if (cnt == 0) continue;
-                    int32_t at = 0;
-                    if (lane == 0) at = atomicAdd(&s_size, cnt);
-                    at = __shfl(at, 0, kWave);
-                    if (fresh[j]) list[at + (int32_t)lanes_below(mask)] = w[j];
-                }
+                append_block(list, &s_size, w, fresh);
             }
             __syncthreads();
             head += nb;
