@@ -55,6 +55,8 @@ def workload(name: str):
         return configs.c1()
     if name == "c2":
         return configs.c2()
+    if name == "c3":
+        return configs.c3()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -110,7 +112,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
