@@ -7,24 +7,23 @@
 
 #include <algorithm>
 #include <chrono>
-#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "../../include/imm.h"
-#include "kernels.hpp"
+#include "host.hpp"
 
 using namespace imm;
 
 namespace {
-
 thread_local std::string g_err;
+}
 
-imm_status fail(imm_status st, const char* fmt, ...) {
+imm_status imm::fail(imm_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -34,145 +33,8 @@ imm_status fail(imm_status st, const char* fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(expr)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(e_ == hipErrorOutOfMemory ? IMM_ENOMEM : IMM_EDEVICE, "%s: %s (%s:%d)", \
-                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                \
-    } while (0)
-
-#define IMM_TRY(expr)                  \
-    do {                               \
-        imm_status s_ = (expr);        \
-        if (s_ != IMM_OK) return s_;   \
-    } while (0)
-
-constexpr int64_t kMaxSets = (int64_t)INT32_MAX;   // RR index and counters fit int32
-
-template <typename T>
-imm_status dalloc(T** p, int64_t count) {
-    *p = nullptr;
-    if (count <= 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(IMM_ENOMEM, "hipMalloc of %lld bytes failed: %s",
-                    (long long)(sizeof(T) * count), hipGetErrorString(e));
-    }
-    return IMM_OK;
-}
-
-template <typename T>
-void dfree(T*& p) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
-
-// Grow a device array to at least `need` elements, keeping the first `keep` elements.
-template <typename T>
-imm_status dgrow(T** p, int64_t* cap, int64_t need, int64_t keep, hipStream_t s) {
-    if (need <= *cap) return IMM_OK;
-    int64_t nc = *cap > 0 ? *cap : 1024;
-    while (nc < need) nc *= 2;
-    T* q = nullptr;
-    IMM_TRY(dalloc(&q, nc));
-    if (keep > *cap) keep = *cap;
-    if (*p && keep > 0) {
-        hipError_t e = hipMemcpyAsync(q, *p, sizeof(T) * (size_t)keep, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            (void)hipFree(q);
-            return fail(IMM_EDEVICE, "grow copy failed: %s", hipGetErrorString(e));
-        }
-    }
-    if (*p) (void)hipFree(*p);
-    *p = q;
-    *cap = nc;
-    return IMM_OK;
-}
-
-double now_s() {
+double imm::now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-}  // namespace
-
-// ------------------------------------------------------------------------------------
-// objects
-// ------------------------------------------------------------------------------------
-struct imm_graph {
-    int device = 0;
-    int32_t n = 0;
-    int64_t m = 0;
-    VRec* vrec = nullptr;
-    int32_t* src = nullptr;
-    uint32_t* thr = nullptr;     // IC thresholds (padded to a multiple of 4 edges)
-    uint32_t* cum = nullptr;     // LT cumulative thresholds
-    bool has_ic = false, has_lt = false;
-    bool ic_uniform = false;     // every vertex has one common IC threshold
-    int cus = 0;
-};
-
-struct imm_pool {
-    const imm_graph* g = nullptr;
-    imm_model model = IMM_IC;
-    uint64_t seed = 0;
-    int64_t count = 0;
-
-    int64_t cap_sets = 0;
-    int64_t* rr_start = nullptr;
-    int32_t* rr_len = nullptr;
-    int64_t cap_ids = 0;
-    int32_t* ids = nullptr;
-    uint32_t* hist = nullptr;
-    PoolCounters* ctr = nullptr;
-    PoolCounters* host_ctr = nullptr;   // pinned mirror
-
-    int64_t cap_lists = 0;
-    uint32_t* heavy_list = nullptr;     // light -> heavy queue
-    uint32_t* cap_list = nullptr;       // id-buffer capacity misses
-    uint32_t* retry_list = nullptr;
-
-    int grid = 0;                       // light launch: blocks of 256 threads
-    int64_t vis_words = 0;
-    uint32_t* visited = nullptr;        // grid * 4 bitmaps
-    int64_t hslots = 0;                 // heavy slots (IC: workgroups, LT: waves)
-    uint32_t* hvisited = nullptr;
-    int32_t* hlist = nullptr;
-    int64_t budget = 4096;              // light-wave group budget per set
-    int heavy_block = 256;              // threads per heavy set (256 or 1024)
-
-    // selection workspace
-    int32_t* h = nullptr;
-    uint32_t* hist_tmp = nullptr;
-    int64_t* inv_off = nullptr;
-    int64_t* scan_tmp = nullptr;
-    uint32_t* cursor = nullptr;
-    int64_t cap_inv = 0;
-    uint32_t* inv = nullptr;
-    int64_t cap_cov = 0;
-    uint8_t* covered = nullptr;
-    int64_t cap_k = 0;
-    unsigned long long* keys = nullptr;
-    int32_t* seeds = nullptr;
-    unsigned long long* n_covered = nullptr;
-    int32_t* host_seeds = nullptr;      // pinned, cap_k
-    unsigned long long* host_cov = nullptr;
-
-    // HIP events bracketing each RR-generation kernel launch
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double kernel_s = 0.0;               // light kernel (IC) / walk kernel (LT)
-    int64_t kernel_launches = 0;
-    double heavy_s = 0.0;                // heavy kernel (IC) / HBM-list walk kernel (LT)
-    int64_t heavy_launches = 0;
-};
-
-static unsigned long long sum64(const unsigned long long* v) {
-    unsigned long long t = 0;
-    for (int i = 0; i < 64; ++i) t += v[i];
-    return t;
 }
 
 // ------------------------------------------------------------------------------------
@@ -186,6 +48,9 @@ double rt_log(double x) {
     return std::log(v);
 }
 constexpr double kE = 2.718281828459045;
+}  // namespace
+
+namespace imm {
 
 double log_binom(int64_t n, int64_t k) {
     double acc = 0.0;
@@ -213,7 +78,74 @@ int32_t estimation_rounds(int64_t n) {
     while (b < 63 && ((int64_t)1 << b) <= n) ++b;
     return b - 2;
 }
-}  // namespace
+
+// ---- ImmPlan ---------------------------------------------------------------------------
+imm_status ImmPlan::init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_) {
+    if (k_ < 1 || k_ > n_) return fail(IMM_EINVAL, "k = %d outside [1, n]", k_);
+    if (!(eps_ > 0.0 && eps_ < 1.0)) return fail(IMM_EINVAL, "eps = %g outside (0, 1)", eps_);
+    if (!(ell_ > 0.0)) return fail(IMM_EINVAL, "ell = %g must be > 0", ell_);
+    *this = ImmPlan();
+    n = n_;
+    k = k_;
+    eps = eps_;
+    ell = ell_;
+    fresh = fresh_;
+    lp = ell_prime(n, ell);
+    ep = std::sqrt(2.0) * eps;
+    lam1 = lambda_prime(n, k, eps, lp);
+    lam2 = lambda_star(n, k, eps, lp);
+    rounds = estimation_rounds(n);
+    if (rounds < 1) return enter_final();
+    return IMM_OK;
+}
+
+imm_status ImmPlan::enter_final() {
+    final_phase = true;
+    const double want = std::ceil(lam2 / lb);
+    if (want > (double)kMaxSets) return fail(IMM_ECAPACITY, "theta = %g too large", want);
+    theta = (int64_t)want;
+    first = fresh ? used : 0;
+    upto = fresh ? used + theta : (theta > used ? theta : used);
+    if (upto > kMaxSets) return fail(IMM_ECAPACITY, "sample end %lld too large", (long long)upto);
+    return IMM_OK;
+}
+
+imm_status ImmPlan::next(int64_t* gen_upto, int64_t* sel_first, int64_t* sel_count) {
+    if (!final_phase) {
+        x = (double)n / (double)((int64_t)1 << i);
+        const double want = std::ceil(lam1 / x);
+        if (want > (double)kMaxSets) return fail(IMM_ECAPACITY, "theta_%d = %g too large", i, want);
+        const int64_t th = (int64_t)want;
+        if (th > used) used = th;
+        *gen_upto = used;
+        *sel_first = 0;
+        *sel_count = used;
+        return IMM_OK;
+    }
+    *gen_upto = upto;
+    *sel_first = first;
+    *sel_count = upto - first;
+    return IMM_OK;
+}
+
+imm_status ImmPlan::complete(int64_t cov) {
+    ++phases;
+    covered = cov;
+    if (final_phase) {
+        done = true;
+        return IMM_OK;
+    }
+    if ((double)n * (double)cov / (double)used >= (1.0 + ep) * x) {
+        lb = (double)n * (double)cov / (double)used / (1.0 + ep);
+        return enter_final();
+    }
+    if (++i > rounds) return enter_final();
+    return IMM_OK;
+}
+
+}  // namespace imm
+
+
 
 extern "C" double imm_log_binom(int64_t n, int64_t k) { return log_binom(n, k); }
 extern "C" double imm_lambda_prime(int64_t n, int64_t k, double eps, double ell) {
@@ -390,25 +322,15 @@ extern "C" imm_status imm_pool_destroy(imm_pool* p) {
     dfree(p->ids);
     dfree(p->hist);
     dfree(p->ctr);
-    if (p->host_ctr) (void)hipHostFree(p->host_ctr);
+    hfree(p->host_ctr);
     dfree(p->heavy_list);
     dfree(p->cap_list);
     dfree(p->retry_list);
     dfree(p->visited);
     dfree(p->hvisited);
     dfree(p->hlist);
-    dfree(p->h);
-    dfree(p->hist_tmp);
-    dfree(p->inv_off);
-    dfree(p->scan_tmp);
-    dfree(p->cursor);
-    dfree(p->inv);
-    dfree(p->covered);
-    dfree(p->keys);
-    dfree(p->seeds);
-    dfree(p->n_covered);
-    if (p->host_seeds) (void)hipHostFree(p->host_seeds);
-    if (p->host_cov) (void)hipHostFree(p->host_cov);
+    p->sel.release();
+    p->launch.release();
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
     delete p;
@@ -431,7 +353,6 @@ static imm_status pool_init(imm_pool* p) {
     HIP_TRY(hipMemset(p->ctr, 0, sizeof(PoolCounters)));
     HIP_TRY(hipMemset(p->visited, 0, sizeof(uint32_t) * (size_t)(p->grid * 4 * p->vis_words)));
     HIP_TRY(hipHostMalloc((void**)&p->host_ctr, sizeof(PoolCounters), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc((void**)&p->host_cov, sizeof(unsigned long long), hipHostMallocDefault));
     memset(p->host_ctr, 0, sizeof(PoolCounters));
     HIP_TRY(hipEventCreate(&p->ev0));
     HIP_TRY(hipEventCreate(&p->ev1));
@@ -576,7 +497,7 @@ static imm_status run_heavy(imm_pool* p, uint32_t n_queue, hipStream_t s) {
     return IMM_OK;
 }
 
-static imm_status pool_generate(imm_pool* p, int64_t upto, hipStream_t s) {
+imm_status imm::pool_generate(imm_pool* p, int64_t upto, hipStream_t s) {
     if (upto <= p->count) return IMM_OK;
     if (upto > kMaxSets) return fail(IMM_ECAPACITY, "RR index %lld exceeds 2^31-1", (long long)upto);
     const int64_t first = p->count, cnt = upto - first;
@@ -627,7 +548,7 @@ extern "C" imm_status imm_generate_rr(imm_pool* p, int64_t upto, void* stream) {
     return pool_generate(p, upto, (hipStream_t)stream);
 }
 
-static imm_status check_range(const imm_pool* p, int64_t first, int64_t count) {
+imm_status imm::check_range(const imm_pool* p, int64_t first, int64_t count) {
     if (first < 0 || count < 0 || first + count > p->count)
         return fail(IMM_EINVAL, "range [%lld, %lld) outside pool of %lld sets", (long long)first,
                     (long long)(first + count), (long long)p->count);
@@ -673,16 +594,16 @@ extern "C" imm_status imm_rr_export(const imm_pool* pc, int64_t first, int64_t c
     return done(IMM_OK);
 }
 
-static imm_status range_hist(imm_pool* p, int64_t first, int64_t count, const uint32_t** out,
-                             hipStream_t s) {
+static imm_status range_hist(imm_pool* p, SelectWs* w, int64_t first, int64_t count,
+                             const uint32_t** out, hipStream_t s) {
     if (first == 0 && count == p->count) {
         *out = p->hist;
         return IMM_OK;
     }
-    if (!p->hist_tmp) IMM_TRY(dalloc(&p->hist_tmp, p->g->n));
-    HIP_TRY(launch_fill_u32(p->hist_tmp, p->g->n, 0u, s));
-    HIP_TRY(launch_hist_range(p->rr_start, p->rr_len, p->ids, first, count, p->hist_tmp, s));
-    *out = p->hist_tmp;
+    if (!w->hist_tmp) IMM_TRY(dalloc(&w->hist_tmp, p->g->n));
+    HIP_TRY(launch_fill_u32(w->hist_tmp, p->g->n, 0u, s));
+    HIP_TRY(launch_hist_range(p->rr_start, p->rr_len, p->ids, first, count, w->hist_tmp, s));
+    *out = w->hist_tmp;
     return IMM_OK;
 }
 
@@ -692,7 +613,7 @@ extern "C" imm_status imm_rr_histogram(const imm_pool* pc, int64_t first, int64_
     imm_pool* p = const_cast<imm_pool*>(pc);
     IMM_TRY(check_range(p, first, count));
     const uint32_t* h = nullptr;
-    IMM_TRY(range_hist(p, first, count, &h, nullptr));
+    IMM_TRY(range_hist(p, &p->sel, first, count, &h, nullptr));
     HIP_TRY(hipMemcpy(hist_out, h, sizeof(uint32_t) * (size_t)p->g->n, hipMemcpyDeviceToHost));
     return IMM_OK;
 }
@@ -700,65 +621,147 @@ extern "C" imm_status imm_rr_histogram(const imm_pool* pc, int64_t first, int64_
 // ------------------------------------------------------------------------------------
 // selection
 // ------------------------------------------------------------------------------------
-static imm_status ensure_select(imm_pool* p, int64_t count, int32_t k) {
+int64_t SelectWs::bytes() const {
+    int64_t b = 0;
+    if (h) b += n * (4 + 4 + 8 + 4) + 8;
+    b += cap_inv * 4 + cap_cov * 4 + cap_k * 12;
+    return b;
+}
+
+void SelectWs::release() {
+    dfree(h);
+    dfree(hist_tmp);
+    dfree(inv_off);
+    dfree(scan_tmp);
+    dfree(cursor);
+    dfree(inv);
+    dfree(covered);
+    dfree(keys);
+    dfree(seeds);
+    dfree(n_covered);
+    hfree(host_seeds);
+    hfree(host_cov);
+    cap_inv = cap_cov = cap_k = 0;
+}
+
+void SelectLaunch::release() {
+    dfree(d_inst);
+    dfree(bar);
+    hfree(host_bar);
+    cap = 0;
+}
+
+int64_t imm_pool::bytes() const {
+    int64_t b = cap_sets * 12 + cap_ids * 4 + (int64_t)g->n * 4 + cap_lists * 12;
+    b += (int64_t)grid * 4 * vis_words * 4 + hslots * (vis_words * 4 + (int64_t)g->n * 4);
+    return b + sel.bytes();
+}
+
+static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t k) {
     const int64_t n = p->g->n;
-    if (!p->h) {
-        IMM_TRY(dalloc(&p->h, n));
-        IMM_TRY(dalloc(&p->inv_off, n + 1));
-        IMM_TRY(dalloc(&p->scan_tmp, scan_tmp_elems(n)));
-        IMM_TRY(dalloc(&p->cursor, n));
-        IMM_TRY(dalloc(&p->n_covered, 1));
+    if (!w->h) {
+        w->n = n;
+        IMM_TRY(dalloc(&w->h, n));
+        IMM_TRY(dalloc(&w->inv_off, n + 1));
+        IMM_TRY(dalloc(&w->scan_tmp, scan_tmp_elems(n)));
+        IMM_TRY(dalloc(&w->cursor, n));
+        IMM_TRY(dalloc(&w->n_covered, 1));
+        HIP_TRY(hipHostMalloc((void**)&w->host_cov, sizeof(unsigned long long), hipHostMallocDefault));
     }
     const int64_t members = (int64_t)sum64(p->host_ctr->placed);
-    if (members > p->cap_inv) {
-        dfree(p->inv);
+    if (members > w->cap_inv) {
+        dfree(w->inv);
         int64_t c = members + members / 4 + 1024;
-        IMM_TRY(dalloc(&p->inv, c));
-        p->cap_inv = c;
+        IMM_TRY(dalloc(&w->inv, c));
+        w->cap_inv = c;
     }
-    if (count > p->cap_cov) {
-        dfree(p->covered);
+    if (count > w->cap_cov) {
+        dfree(w->covered);
         int64_t c = count + count / 4 + 1024;
-        IMM_TRY(dalloc(&p->covered, c));
-        p->cap_cov = c;
+        IMM_TRY(dalloc(&w->covered, c));
+        w->cap_cov = c;
     }
-    if (k > p->cap_k) {
-        dfree(p->keys);
-        dfree(p->seeds);
-        if (p->host_seeds) (void)hipHostFree(p->host_seeds);
-        p->host_seeds = nullptr;
-        IMM_TRY(dalloc(&p->keys, k));
-        IMM_TRY(dalloc(&p->seeds, k));
-        HIP_TRY(hipHostMalloc((void**)&p->host_seeds, sizeof(int32_t) * (size_t)k, hipHostMallocDefault));
-        p->cap_k = k;
+    if (k > w->cap_k) {
+        dfree(w->keys);
+        dfree(w->seeds);
+        hfree(w->host_seeds);
+        IMM_TRY(dalloc(&w->keys, k));
+        IMM_TRY(dalloc(&w->seeds, k));
+        HIP_TRY(hipHostMalloc((void**)&w->host_seeds, sizeof(int32_t) * (size_t)k, hipHostMallocDefault));
+        w->cap_k = k;
     }
+    return IMM_OK;
+}
+
+imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t k,
+                               hipStream_t s, SelInst* out) {
+    const int32_t n = p->g->n;
+    IMM_TRY(ensure_select(p, w, count, k));
+    const uint32_t* hsrc = nullptr;
+    IMM_TRY(range_hist(p, w, first, count, &hsrc, s));
+    HIP_TRY(launch_copy_hist(hsrc, w->h, n, s));
+    HIP_TRY(launch_scan_u32(hsrc, n, w->inv_off, w->scan_tmp, s));
+    HIP_TRY(launch_fill_u32(w->cursor, n, 0u, s));
+    HIP_TRY(launch_inv_scatter(p->rr_start, p->rr_len, p->ids, first, count, w->inv_off, w->cursor,
+                               w->inv, s));
+    HIP_TRY(launch_fill_u32(w->covered, count, 0u, s));
+    HIP_TRY(launch_fill_u64(w->keys, k, 0ull, s));
+    HIP_TRY(launch_fill_u64(w->n_covered, 1, 0ull, s));
+    w->k = k;
+    SelInst si{};
+    si.n = n;
+    si.k = k;
+    si.first = first;
+    si.count = count;
+    si.h = w->h;
+    si.inv_off = w->inv_off;
+    si.inv = w->inv;
+    si.rr_start = p->rr_start;
+    si.rr_len = p->rr_len;
+    si.ids = p->ids;
+    si.covered = w->covered;
+    si.keys = w->keys;
+    si.seeds = w->seeds;
+    si.n_covered = w->n_covered;
+    *out = si;
+    return IMM_OK;
+}
+
+imm_status imm::select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,
+                           hipStream_t s) {
+    if (ninst > L->cap) {
+        L->release();
+        IMM_TRY(dalloc(&L->d_inst, ninst));
+        IMM_TRY(dalloc(&L->bar, 1));
+        HIP_TRY(hipHostMalloc((void**)&L->host_bar, sizeof(GridBarrier), hipHostMallocDefault));
+        L->cap = ninst;
+    }
+    int32_t maxk = 0;
+    for (int32_t i = 0; i < ninst; ++i) maxk = std::max(maxk, inst[i].k);
+    HIP_TRY(hipMemcpyAsync(L->d_inst, inst, sizeof(SelInst) * (size_t)ninst, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(L->bar, 0, sizeof(GridBarrier), s));
+    HIP_TRY(launch_select_coop(L->d_inst, ninst, maxk, L->bar, s));
+    HIP_TRY(hipMemcpyAsync(L->host_bar, L->bar, sizeof(GridBarrier), hipMemcpyDeviceToHost, s));
+    for (int32_t i = 0; i < ninst; ++i) {
+        SelectWs* w = ws[i];
+        HIP_TRY(hipMemcpyAsync(w->host_seeds, w->seeds, sizeof(int32_t) * (size_t)w->k,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(w->host_cov, w->n_covered, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (L->host_bar->err) return fail(IMM_EDEVICE, "selection grid barrier timed out");
     return IMM_OK;
 }
 
 static imm_status pool_select(imm_pool* p, int64_t first, int64_t count, int32_t k,
                               int32_t* seeds_out, int64_t* covered_out, hipStream_t s) {
-    const int32_t n = p->g->n;
-    IMM_TRY(ensure_select(p, count, k));
-    const uint32_t* hsrc = nullptr;
-    IMM_TRY(range_hist(p, first, count, &hsrc, s));
-    HIP_TRY(launch_copy_hist(hsrc, p->h, n, s));
-    HIP_TRY(launch_scan_u32(hsrc, n, p->inv_off, p->scan_tmp, s));
-    HIP_TRY(launch_fill_u32(p->cursor, n, 0u, s));
-    HIP_TRY(launch_inv_scatter(p->rr_start, p->rr_len, p->ids, first, count, p->inv_off, p->cursor,
-                               p->inv, s));
-    HIP_TRY(launch_fill_u8(p->covered, count, (uint8_t)0, s));
-    HIP_TRY(launch_fill_u64(p->keys, k, 0ull, s));
-    HIP_TRY(launch_fill_u64(p->n_covered, 1, 0ull, s));
-    for (int32_t round = 0; round < k; ++round) {
-        HIP_TRY(launch_argmax(p->h, n, round, p->seeds, p->keys, s));
-        HIP_TRY(launch_cover(p->keys, round, p->inv_off, p->inv, p->rr_start, p->rr_len, p->ids,
-                             first, p->covered, p->h, p->seeds, p->n_covered, s));
-    }
-    HIP_TRY(hipMemcpyAsync(p->host_seeds, p->seeds, sizeof(int32_t) * (size_t)k, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(p->host_cov, p->n_covered, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (seeds_out) memcpy(seeds_out, p->host_seeds, sizeof(int32_t) * (size_t)k);
-    if (covered_out) *covered_out = (int64_t)*p->host_cov;
+    SelInst si;
+    IMM_TRY(select_prepare(p, &p->sel, first, count, k, s, &si));
+    SelectWs* w = &p->sel;
+    IMM_TRY(select_run(&p->launch, &w, &si, 1, s));
+    if (seeds_out) memcpy(seeds_out, w->host_seeds, sizeof(int32_t) * (size_t)k);
+    if (covered_out) *covered_out = (int64_t)*w->host_cov;
     return IMM_OK;
 }
 
@@ -775,67 +778,37 @@ extern "C" imm_status imm_select_seeds(imm_pool* p, int64_t first, int64_t count
 // ------------------------------------------------------------------------------------
 static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh,
                           hipStream_t s, int32_t* seeds_out, imm_info* info) {
-    const int64_t n = p->g->n;
-    if (k < 1 || k > n) return fail(IMM_EINVAL, "k = %d outside [1, n]", k);
-    if (!(eps > 0.0 && eps < 1.0)) return fail(IMM_EINVAL, "eps = %g outside (0, 1)", eps);
-    if (!(ell > 0.0)) return fail(IMM_EINVAL, "ell = %g must be > 0", ell);
     if (!seeds_out) return fail(IMM_EINVAL, "seeds_out is NULL");
     const double t0 = now_s();
     double t_gen = 0.0, t_sel = 0.0;
     const double kernel_s0 = p->kernel_s, heavy_s0 = p->heavy_s;
     const int64_t launches0 = p->kernel_launches, heavy0 = p->heavy_launches;
-    const double lp = ell_prime(n, ell);
-    const double ep = std::sqrt(2.0) * eps;
-    const double lam1 = lambda_prime(n, k, eps, lp);
-    const double lam2 = lambda_star(n, k, eps, lp);
-    const int32_t rounds = estimation_rounds(n);
-    double lb = 1.0;
-    int64_t used = 0, cov = 0;
-    int32_t phases = 0;
-    for (int32_t i = 1; i <= rounds; ++i) {
-        const double x = (double)n / (double)((int64_t)1 << i);
-        const double want = std::ceil(lam1 / x);
-        if (want > (double)kMaxSets) return fail(IMM_ECAPACITY, "theta_%d = %g too large", i, want);
-        const int64_t th = (int64_t)want;
-        if (th > used) used = th;
-        double ta = now_s();
-        IMM_TRY(pool_generate(p, used, s));
-        double tb = now_s();
-        IMM_TRY(pool_select(p, 0, used, k, seeds_out, &cov, s));
+    ImmPlan plan;
+    IMM_TRY(plan.init(p->g->n, k, eps, ell, fresh));
+    while (!plan.done) {
+        int64_t upto, first, count, cov = 0;
+        IMM_TRY(plan.next(&upto, &first, &count));
+        const double ta = now_s();
+        IMM_TRY(pool_generate(p, upto, s));
+        const double tb = now_s();
+        IMM_TRY(pool_select(p, first, count, k, seeds_out, &cov, s));
         t_gen += tb - ta;
         t_sel += now_s() - tb;
-        ++phases;
-        if ((double)n * (double)cov / (double)used >= (1.0 + ep) * x) {
-            lb = (double)n * (double)cov / (double)used / (1.0 + ep);
-            break;
-        }
+        IMM_TRY(plan.complete(cov));
     }
-    const double want = std::ceil(lam2 / lb);
-    if (want > (double)kMaxSets) return fail(IMM_ECAPACITY, "theta = %g too large", want);
-    const int64_t theta = (int64_t)want;
-    const int64_t first = fresh ? used : 0;
-    const int64_t upto = fresh ? used + theta : (theta > used ? theta : used);
-    if (upto > kMaxSets) return fail(IMM_ECAPACITY, "sample end %lld too large", (long long)upto);
-    double ta = now_s();
-    IMM_TRY(pool_generate(p, upto, s));
-    double tb = now_s();
-    IMM_TRY(pool_select(p, first, upto - first, k, seeds_out, &cov, s));
-    t_gen += tb - ta;
-    t_sel += now_s() - tb;
-    ++phases;
     if (info) {
         memset(info, 0, sizeof *info);
-        info->theta = theta;
-        info->num_rr = upto;
-        info->covered = cov;
+        info->theta = plan.theta;
+        info->num_rr = plan.upto;
+        info->covered = plan.covered;
         info->edges_examined = (int64_t)(sum64(p->host_ctr->edges) + sum64(p->host_ctr->hedges));
         info->edges_heavy = (int64_t)sum64(p->host_ctr->hedges);
         info->pool_ids = (int64_t)sum64(p->host_ctr->placed);
-        info->phases = phases;
-        info->lb = lb;
-        info->spread_est = (double)n * (double)cov / (double)(upto - first);
-        info->lambda_prime = lam1;
-        info->lambda_star = lam2;
+        info->phases = plan.phases;
+        info->lb = plan.lb;
+        info->spread_est = plan.spread_est();
+        info->lambda_prime = plan.lam1;
+        info->lambda_star = plan.lam2;
         info->t_generate_s = t_gen;
         info->t_select_s = t_sel;
         info->t_total_s = now_s() - t0;

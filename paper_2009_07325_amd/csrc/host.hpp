@@ -1,0 +1,240 @@
+// Internal host-side declarations of libimm (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/imm.h"
+#include "kernels.hpp"
+
+namespace imm {
+
+// ---- errors and device memory ---------------------------------------------------------
+imm_status fail(imm_status st, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::imm::fail(e_ == hipErrorOutOfMemory ? IMM_ENOMEM : IMM_EDEVICE,      \
+                               "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,  \
+                               __LINE__);                                                 \
+    } while (0)
+
+#define IMM_TRY(expr)                  \
+    do {                               \
+        imm_status s_ = (expr);        \
+        if (s_ != IMM_OK) return s_;   \
+    } while (0)
+
+constexpr int64_t kMaxSets = (int64_t)INT32_MAX;   // RR index and counters fit int32
+
+template <typename T>
+imm_status dalloc(T** p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(IMM_ENOMEM, "hipMalloc of %lld bytes failed: %s",
+                    (long long)(sizeof(T) * count), hipGetErrorString(e));
+    }
+    return IMM_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename T>
+void hfree(T*& p) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+}
+
+// Grow a device array to at least `need` elements, keeping the first `keep` elements.
+template <typename T>
+imm_status dgrow(T** p, int64_t* cap, int64_t need, int64_t keep, hipStream_t s) {
+    if (need <= *cap) return IMM_OK;
+    int64_t nc = *cap > 0 ? *cap : 1024;
+    while (nc < need) nc *= 2;
+    T* q = nullptr;
+    IMM_TRY(dalloc(&q, nc));
+    if (keep > *cap) keep = *cap;
+    if (*p && keep > 0) {
+        hipError_t e = hipMemcpyAsync(q, *p, sizeof(T) * (size_t)keep, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipFree(q);
+            return fail(IMM_EDEVICE, "grow copy failed: %s", hipGetErrorString(e));
+        }
+    }
+    if (*p) (void)hipFree(*p);
+    *p = q;
+    *cap = nc;
+    return IMM_OK;
+}
+
+double now_s();
+
+inline unsigned long long sum64(const unsigned long long* v) {
+    unsigned long long t = 0;
+    for (int i = 0; i < 64; ++i) t += v[i];
+    return t;
+}
+
+// ---- IMM sample sizes and the LB / theta state machine --------------------------------
+double log_binom(int64_t n, int64_t k);
+double ell_prime(int64_t n, double ell);
+double lambda_prime(int64_t n, int64_t k, double eps, double lp);
+double lambda_star(int64_t n, int64_t k, double eps, double lp);
+int32_t estimation_rounds(int64_t n);
+
+// One IMM solve as a sequence of selections (gIM Alg. 2, then Alg. 1).  next() names the
+// RR range of the next selection and how far the pool must extend; complete() takes the
+// covered count of that selection.  Every solve path (plain, served, batched) drives
+// this one object, so they all compute the same doubles in the same order.
+struct ImmPlan {
+    int64_t n = 0;
+    int32_t k = 0;
+    double eps = 0, ell = 0;
+    int32_t fresh = 0;
+    double lp = 0, ep = 0, lam1 = 0, lam2 = 0;
+    int32_t rounds = 0;
+    // progress
+    int32_t i = 1;
+    int64_t used = 0;
+    double x = 0.0;
+    double lb = 1.0;
+    bool final_phase = false, done = false;
+    int64_t theta = 0, first = 0, upto = 0;
+    int32_t phases = 0;
+    int64_t covered = 0;
+
+    imm_status init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_);
+    imm_status next(int64_t* gen_upto, int64_t* sel_first, int64_t* sel_count);
+    imm_status complete(int64_t cov);
+    double spread_est() const { return (double)n * (double)covered / (double)(upto - first); }
+
+  private:
+    imm_status enter_final();
+};
+
+}  // namespace imm
+
+// ---- library objects -------------------------------------------------------------------
+struct imm_graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t m = 0;
+    imm::VRec* vrec = nullptr;
+    int32_t* src = nullptr;
+    uint32_t* thr = nullptr;     // IC thresholds (padded to a multiple of 4 edges)
+    uint32_t* cum = nullptr;     // LT cumulative thresholds
+    bool has_ic = false, has_lt = false;
+    bool ic_uniform = false;     // every vertex has one common IC threshold
+    int cus = 0;
+};
+
+namespace imm {
+
+// Selection workspace: one per concurrent selection (a pool has one; a server has one per
+// active query).
+struct SelectWs {
+    int64_t n = 0;
+    int32_t* h = nullptr;
+    uint32_t* hist_tmp = nullptr;
+    int64_t* inv_off = nullptr;
+    int64_t* scan_tmp = nullptr;
+    uint32_t* cursor = nullptr;
+    int64_t cap_inv = 0;
+    uint32_t* inv = nullptr;
+    int64_t cap_cov = 0;
+    uint32_t* covered = nullptr;
+    int64_t cap_k = 0;
+    unsigned long long* keys = nullptr;
+    int32_t* seeds = nullptr;
+    unsigned long long* n_covered = nullptr;
+    int32_t* host_seeds = nullptr;            // pinned, cap_k
+    unsigned long long* host_cov = nullptr;   // pinned
+    int32_t k = 0;                            // of the prepared selection
+
+    int64_t bytes() const;
+    void release();
+};
+
+// Device descriptors + barrier of one cooperative selection launch (any number of
+// instances up to the kernel's limit).
+struct SelectLaunch {
+    int64_t cap = 0;
+    SelInst* d_inst = nullptr;
+    GridBarrier* bar = nullptr;
+    GridBarrier* host_bar = nullptr;          // pinned
+    void release();
+};
+
+}  // namespace imm
+
+struct imm_pool {
+    const imm_graph* g = nullptr;
+    imm_model model = IMM_IC;
+    uint64_t seed = 0;
+    int64_t count = 0;
+
+    int64_t cap_sets = 0;
+    int64_t* rr_start = nullptr;
+    int32_t* rr_len = nullptr;
+    int64_t cap_ids = 0;
+    int32_t* ids = nullptr;
+    uint32_t* hist = nullptr;
+    imm::PoolCounters* ctr = nullptr;
+    imm::PoolCounters* host_ctr = nullptr;   // pinned mirror
+
+    int64_t cap_lists = 0;
+    uint32_t* heavy_list = nullptr;     // light -> heavy queue
+    uint32_t* cap_list = nullptr;       // id-buffer capacity misses
+    uint32_t* retry_list = nullptr;
+
+    int grid = 0;                       // light launch: blocks of 256 threads
+    int64_t vis_words = 0;
+    uint32_t* visited = nullptr;        // grid * 4 bitmaps
+    int64_t hslots = 0;                 // heavy slots (IC: workgroups, LT: waves)
+    uint32_t* hvisited = nullptr;
+    int32_t* hlist = nullptr;
+    int64_t budget = 4096;              // light-wave group budget per set
+    int heavy_block = 256;              // threads per heavy set (256 or 1024)
+
+    imm::SelectWs sel;                  // selection workspace of imm_select_seeds / solve
+    imm::SelectLaunch launch;
+
+    // HIP events bracketing each RR-generation kernel launch
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_s = 0.0;               // light kernel (IC) / walk kernel (LT)
+    int64_t kernel_launches = 0;
+    double heavy_s = 0.0;                // heavy kernel (IC) / HBM-list walk kernel (LT)
+    int64_t heavy_launches = 0;
+
+    int64_t bytes() const;               // device memory held
+};
+
+namespace imm {
+
+imm_status pool_generate(imm_pool* p, int64_t upto, hipStream_t s);
+imm_status check_range(const imm_pool* p, int64_t first, int64_t count);
+
+// Launches the per-selection setup kernels (counts, inverted index, clears) on `s` and
+// fills `out` with the instance descriptor.
+imm_status select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t k,
+                          hipStream_t s, SelInst* out);
+// Runs all rounds of every prepared instance in one cooperative launch, then copies each
+// instance's seeds and covered count to its workspace's pinned buffers (synchronises s).
+imm_status select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,
+                      hipStream_t s);
+
+}  // namespace imm

@@ -95,12 +95,36 @@ hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, co
                               int64_t first, int64_t count, const int64_t* inv_off,
                               uint32_t* cursor, uint32_t* inv, hipStream_t s);
 hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStream_t s);
-hipError_t launch_argmax(int32_t* h, int32_t n, int32_t round, const int32_t* seeds,
-                         unsigned long long* keys, hipStream_t s);
-hipError_t launch_cover(const unsigned long long* keys, int32_t round, const int64_t* inv_off,
-                        const uint32_t* inv, const int64_t* rr_start, const int32_t* rr_len,
-                        const int32_t* ids, int64_t first, uint8_t* covered, int32_t* h,
-                        int32_t* seeds, unsigned long long* n_covered, hipStream_t s);
+// All k rounds of greedy selection for one or more instances in one cooperative launch:
+// per round a segmented argmax over every instance's counters, a grid barrier, the cover
+// step of every instance, a grid barrier.
+struct SelInst {
+    int32_t n;
+    int32_t k;
+    int64_t first;                 // RR range [first, first + count) of the pool
+    int64_t count;
+    int32_t* h;                    // counters (n), -1 marks chosen vertices
+    const int64_t* inv_off;        // inverted index (n + 1)
+    const uint32_t* inv;           // relative RR indices
+    const int64_t* rr_start;
+    const int32_t* rr_len;
+    const int32_t* ids;
+    uint32_t* covered;             // count flags
+    unsigned long long* keys;      // k argmax keys (zeroed)
+    int32_t* seeds;                // k
+    unsigned long long* n_covered; // zeroed
+};
+// Arrival counters of a hierarchical grid barrier (zeroed before each launch): block b
+// arrives on sub[b % 16]; the last arrival of a group bumps top; all wait for top.
+struct alignas(64) GridBarrier {
+    unsigned int sub[16][16];      // one 64-byte line per group
+    unsigned int top;
+    unsigned int err;              // set when a barrier wait timed out
+    unsigned int pad[14];
+};
+int select_coop_grid();            // blocks of the cooperative launch (co-resident)
+hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
+                              hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

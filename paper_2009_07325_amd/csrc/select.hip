@@ -205,89 +205,187 @@ hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStre
     return hipGetLastError();
 }
 
-// ---- argmax over the counters ---------------------------------------------------------
+// ---- greedy rounds ------------------------------------------------------------------
 // key(v) = (h[v] + 1) << 32 | (2^32 - 1 - v): the largest key has the largest count and,
-// among equal counts, the smallest id.  Selected vertices hold h = -1 (key high part 0),
-// so any unselected vertex beats them.  The vertex chosen in the previous round is set to
-// -1 here, after its cover kernel has finished.
-constexpr int kArgBlock = 256;
+// among equal counts, the smallest id.  Chosen vertices hold h = -1 (key high part 0), so
+// any vertex not chosen beats them; the vertex chosen in round j - 1 is set to -1 by the
+// argmax of round j, after its cover step has finished.
+// ---- all rounds in one cooperative launch ---------------------------------------------
+constexpr int kCoopBlock = 1024;
+constexpr int kCoopWaves = kCoopBlock / kWave;
+constexpr int kArgTile = kCoopBlock * 4;       // counters per argmax tile
+constexpr int kMaxInst = 1024;                  // instances per launch (LDS tables)
 
-__global__ __launch_bounds__(kArgBlock) void k_argmax(int32_t* __restrict__ h, int32_t n, int32_t round,
-                                                      const int32_t* __restrict__ seeds,
-                                                      unsigned long long* __restrict__ keys) {
-    __shared__ unsigned long long sh[kArgBlock / kWave];
-    const int32_t prev = round > 0 ? seeds[round - 1] : -1;
-    unsigned long long best = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int32_t c = h[i];
-        if ((int32_t)i == prev) {
-            h[i] = -1;
-            c = -1;
-        }
-        if (c >= 0) {
-            const unsigned long long key = ((unsigned long long)(uint32_t)(c + 1) << 32) |
-                                           (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
-            best = key > best ? key : best;
-        }
-    }
-    best = wave_max_u64(best);
-    if (lane_id() == 0) sh[threadIdx.x / kWave] = best;
+template <typename T>
+__device__ __forceinline__ T ld_co(const T* p) {        // coherent load (all XCDs)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_co(T* p, T v) {      // coherent store
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier over all (co-resident) blocks.  Every block first waits for its own memory
+// operations to complete, so once the last block has arrived, everything written before
+// the barrier is visible to coherent (agent-scope) loads issued after it.  Data shared
+// between blocks inside the kernel is only read and written with such loads, stores and
+// atomics, so no cache write-back or invalidate is needed.  Counters are monotonic
+// (epoch-based) and spread over 16 lines; a wait that exceeds ~2^24 polls sets bar->err
+// and every block leaves, so no wave spins forever.
+__device__ __forceinline__ bool grid_sync(GridBarrier* bar, unsigned int& epoch) {
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    __shared__ int s_ok;
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kArgBlock / kWave; ++w) best = sh[w] > best ? sh[w] : best;
-        if (best) __hip_atomic_fetch_max(keys + round, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int ngroups = gridDim.x < 16 ? gridDim.x : 16u;
+        const unsigned int grp = blockIdx.x % ngroups;
+        const unsigned int gsize = (gridDim.x - grp + ngroups - 1) / ngroups;
+        const unsigned int old = __hip_atomic_fetch_add(&bar->sub[grp][0], 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == (epoch + 1) * gsize) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_fetch_add(&bar->top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const unsigned int target = (epoch + 1) * ngroups;
+        int ok = 1;
+        unsigned int polls = 0;
+        while (ld_co(&bar->top) < target) {
+            if (++polls > (1u << 24) || ld_co(&bar->err)) {
+                st_co(&bar->err, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_ok = ok;
+    }
+    ++epoch;
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __restrict__ inst,
+                                                            int32_t ninst, int32_t maxk,
+                                                            GridBarrier* bar) {
+    __shared__ int64_t tile_pre[kMaxInst + 1];    // argmax tiles per instance, prefix
+    __shared__ int64_t ent_pre[kMaxInst + 1];     // cover entries per instance, prefix
+    __shared__ int64_t ent_beg[kMaxInst];
+    __shared__ int32_t ent_u[kMaxInst];
+    __shared__ unsigned long long red[kCoopWaves];
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    unsigned int epoch = 0;
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < ninst; ++i) {
+            tile_pre[i] = acc;
+            acc += (inst[i].n + kArgTile - 1) / kArgTile;
+        }
+        tile_pre[ninst] = acc;
+    }
+    __syncthreads();
+    const int64_t ntiles = tile_pre[ninst];
+    const int64_t gwave = (int64_t)blockIdx.x * kCoopWaves + wid;
+    const int64_t nwaves = (int64_t)gridDim.x * kCoopWaves;
+
+    for (int32_t round = 0; round < maxk; ++round) {
+        // ---- argmax: tiles of kArgTile counters, any instance still selecting ----
+        for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            int lo = 0, hi = ninst;                      // tile_pre[lo] <= t < tile_pre[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (tile_pre[mid] <= t) lo = mid; else hi = mid;
+            }
+            const SelInst& I = inst[lo];
+            if (round >= I.k) continue;                  // uniform across the block
+            const int32_t prev = round > 0 ? ld_co(I.seeds + round - 1) : -1;
+            const int64_t base = (t - tile_pre[lo]) * kArgTile;
+            unsigned long long best = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t v = base + j * kCoopBlock + tid;
+                if (v < I.n) {
+                    int32_t c = ld_co(I.h + v);
+                    if ((int32_t)v == prev) {
+                        st_co(I.h + v, -1);
+                        c = -1;
+                    }
+                    if (c >= 0) {
+                        const unsigned long long key = ((unsigned long long)(uint32_t)(c + 1) << 32) |
+                                                       (unsigned long long)(0xFFFFFFFFu - (uint32_t)v);
+                        best = key > best ? key : best;
+                    }
+                }
+            }
+            best = wave_max_u64(best);
+            if (lane == 0) red[wid] = best;
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 1; w < kCoopWaves; ++w) best = red[w] > best ? red[w] : best;
+                if (best) __hip_atomic_fetch_max(I.keys + round, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+        if (!grid_sync(bar, epoch)) return;
+        // ---- cover: sets containing each instance's new seed ----
+        if (tid == 0) {
+            int64_t acc = 0;
+            for (int i = 0; i < ninst; ++i) {
+                ent_pre[i] = acc;
+                if (round < inst[i].k) {
+                    const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)ld_co(inst[i].keys + round));
+                    ent_u[i] = u;
+                    ent_beg[i] = inst[i].inv_off[u];
+                    acc += inst[i].inv_off[u + 1] - ent_beg[i];
+                    if (blockIdx.x == 0) st_co(inst[i].seeds + round, u);
+                }
+            }
+            ent_pre[ninst] = acc;
+        }
+        __syncthreads();
+        const int64_t nent = ent_pre[ninst];
+        unsigned long long mine = 0;
+        int mine_inst = -1;
+        for (int64_t e = gwave; e < nent; e += nwaves) {
+            int lo = 0, hi = ninst;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (ent_pre[mid] <= e) lo = mid; else hi = mid;
+            }
+            const SelInst& I = inst[lo];
+            const uint32_t rel = I.inv[ent_beg[lo] + (e - ent_pre[lo])];
+            if (ld_co(I.covered + rel)) continue;         // uniform across the wave
+            if (lane == 0) st_co(I.covered + rel, 1u);
+            if (mine_inst != lo) {
+                if (mine && lane == 0) atomic_add_agent(inst[mine_inst].n_covered, mine);
+                mine = 0;
+                mine_inst = lo;
+            }
+            ++mine;
+            const int64_t s0 = I.rr_start[I.first + rel];
+            const int32_t len = I.rr_len[I.first + rel];
+            for (int32_t q = lane; q < len; q += kWave)
+                __hip_atomic_fetch_add(I.h + I.ids[s0 + q], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (mine && lane == 0) atomic_add_agent(inst[mine_inst].n_covered, mine);
+        if (!grid_sync(bar, epoch)) return;
     }
 }
 
-hipError_t launch_argmax(int32_t* h, int32_t n, int32_t round, const int32_t* seeds,
-                         unsigned long long* keys, hipStream_t s) {
-    int64_t blocks = ((int64_t)n + kArgBlock * 4 - 1) / (kArgBlock * 4);
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    k_argmax<<<(unsigned)blocks, kArgBlock, 0, s>>>(h, n, round, seeds, keys);
-    return hipGetLastError();
+int select_coop_grid() {
+    int dev = 0, cus = 0, nb = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_select_coop, kCoopBlock, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return cus * (nb < 2 ? nb : 2);
 }
 
-// ---- cover: flag the sets containing u, decrement their members' counters -----------
-__global__ __launch_bounds__(256) void k_cover(const unsigned long long* __restrict__ keys, int32_t round,
-                                               const int64_t* __restrict__ inv_off,
-                                               const uint32_t* __restrict__ inv,
-                                               const int64_t* __restrict__ rr_start,
-                                               const int32_t* __restrict__ rr_len,
-                                               const int32_t* __restrict__ ids, int64_t first,
-                                               uint8_t* __restrict__ covered, int32_t* __restrict__ h,
-                                               int32_t* __restrict__ seeds,
-                                               unsigned long long* __restrict__ n_covered) {
-    const int lane = lane_id();
-    const unsigned long long key = keys[round];
-    const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
-    if (blockIdx.x == 0 && threadIdx.x == 0) seeds[round] = u;
-    const int64_t b = inv_off[u], e = inv_off[u + 1];
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-    unsigned long long mine = 0;
-    for (int64_t j = b + wave; j < e; j += nwaves) {
-        const uint32_t rel = inv[j];
-        if (covered[rel]) continue;          // uniform across the wave
-        wave_sync();
-        if (lane == 0) covered[rel] = 1;
-        ++mine;
-        const int64_t s = rr_start[first + rel];
-        const int32_t len = rr_len[first + rel];
-        for (int32_t t = lane; t < len; t += kWave)
-            __hip_atomic_fetch_add(h + ids[s + t], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (lane == 0 && mine) atomic_add_agent(n_covered, mine);
-}
-
-hipError_t launch_cover(const unsigned long long* keys, int32_t round, const int64_t* inv_off,
-                        const uint32_t* inv, const int64_t* rr_start, const int32_t* rr_len,
-                        const int32_t* ids, int64_t first, uint8_t* covered, int32_t* h,
-                        int32_t* seeds, unsigned long long* n_covered, hipStream_t s) {
-    k_cover<<<1024, 256, 0, s>>>(keys, round, inv_off, inv, rr_start, rr_len, ids, first, covered,
-                                 h, seeds, n_covered);
-    return hipGetLastError();
+hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
+                              hipStream_t s) {
+    if (ninst < 1 || ninst > kMaxInst) return hipErrorInvalidValue;
+    void* args[] = {(void*)&inst, (void*)&ninst, (void*)&maxk, (void*)&bar};
+    return hipLaunchCooperativeKernel((const void*)k_select_coop, dim3(select_coop_grid()),
+                                      dim3(kCoopBlock), args, 0, s);
 }
 
 }  // namespace imm
