@@ -170,6 +170,41 @@ imm_status imm_solve(const imm_graph* g, int32_t k, double eps, double ell, imm_
 imm_status imm_solve_pool(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh_final,
                           void* stream, int32_t* seeds_out, imm_info* info);
 
+/* ---- serving (continuous batching over one resident graph) -----------------------------
+ * A server keeps the graph and one RR pool per model (IC with seed_ic, LT with seed_lt;
+ * a model is served when the graph has its encoding) resident in HBM.  Queries are
+ * admitted while fewer than max_active are in flight and the estimated device memory stays
+ * within hbm_budget_bytes; every scheduler tick extends each pool once, to the largest
+ * demand among the active queries (RR sets are shared), and runs the greedy selections of
+ * all active queries in one device launch.  A query's result equals imm_solve on the same
+ * graph with the pool's seed, whatever else is in flight (gIM Sec. I and IV-H motivate
+ * solving IM many times on one graph).  Thread-safe: submit/poll/wait from any thread. */
+typedef struct imm_server imm_server;
+typedef struct {
+    int64_t submitted, completed, rejected, active, queued, ticks;
+    double p50_latency_s, p99_latency_s, mean_latency_s, max_latency_s;
+    double throughput_qps;     /* completed / (last completion - first submission) */
+    int64_t pool_sets_ic, pool_sets_lt;
+    int64_t device_bytes;      /* pools + selection workspaces */
+} imm_server_stats;
+
+imm_status imm_server_create(const imm_graph* g, uint64_t seed_ic, uint64_t seed_lt,
+                             int64_t hbm_budget_bytes, int32_t max_active, imm_server** out);
+/* Queue one query; *ticket identifies it.  IMM_EINVAL for bad arguments (as imm_solve),
+ * IMM_ECAPACITY when it can never fit the memory budget. */
+imm_status imm_server_submit(imm_server* s, int32_t k, double eps, double ell, imm_model model,
+                             int32_t fresh_final, uint64_t* ticket);
+/* Non-blocking: *done = 1 and results written when the query has finished. */
+imm_status imm_server_poll(imm_server* s, uint64_t ticket, int32_t* seeds_out, imm_info* info,
+                           int32_t* done);
+/* Blocks until the query finishes (IMM_EBUSY after timeout_s; timeout_s <= 0 waits
+ * indefinitely).  info->t_total_s is the latency from submission to completion. */
+imm_status imm_server_wait(imm_server* s, uint64_t ticket, double timeout_s, int32_t* seeds_out,
+                           imm_info* info);
+imm_status imm_server_stats_get(imm_server* s, imm_server_stats* out);
+/* Stops the worker (queries still pending are dropped) and frees everything. */
+imm_status imm_server_destroy(imm_server* s);
+
 /* IMM sample-size quantities, exposed for verification (IEEE double, no FMA contraction):
  * ln C(n,k); lambda' of the LB loop; lambda* of the final sample; ell' = ell(1+ln2/ln n). */
 double imm_log_binom(int64_t n, int64_t k);

@@ -28,7 +28,8 @@ EXPORTS = ("imm_init", "imm_last_error", "imm_graph_create", "imm_graph_destroy"
            "imm_graph_info", "imm_graph_export_encoding", "imm_pool_create", "imm_pool_destroy",
            "imm_pool_size", "imm_generate_rr", "imm_rr_export", "imm_rr_histogram",
            "imm_select_seeds", "imm_solve", "imm_solve_pool", "imm_log_binom",
-           "imm_lambda_prime", "imm_lambda_star")
+           "imm_lambda_prime", "imm_lambda_star", "imm_server_create", "imm_server_submit",
+           "imm_server_poll", "imm_server_wait", "imm_server_stats_get", "imm_server_destroy")
 
 
 class ImmError(RuntimeError):
@@ -56,6 +57,19 @@ class ImmInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class ImmServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("mean_latency_s", ctypes.c_double), ("max_latency_s", ctypes.c_double),
+                ("throughput_qps", ctypes.c_double), ("pool_sets_ic", ctypes.c_int64),
+                ("pool_sets_lt", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -88,6 +102,12 @@ def lib() -> ctypes.CDLL:
             "imm_solve": [p, i32, dbl, dbl, ctypes.c_int, ctypes.POINTER(ImmOptions), p,
                           ctypes.POINTER(ImmInfo)],
             "imm_solve_pool": [p, i32, dbl, dbl, i32, p, p, ctypes.POINTER(ImmInfo)],
+            "imm_server_create": [p, u64, u64, i64, i32, pp],
+            "imm_server_submit": [p, i32, dbl, dbl, ctypes.c_int, i32, ctypes.POINTER(ctypes.c_uint64)],
+            "imm_server_poll": [p, u64, p, ctypes.POINTER(ImmInfo), ctypes.POINTER(ctypes.c_int32)],
+            "imm_server_wait": [p, u64, dbl, p, ctypes.POINTER(ImmInfo)],
+            "imm_server_stats_get": [p, ctypes.POINTER(ImmServerStats)],
+            "imm_server_destroy": [p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -233,6 +253,46 @@ def imm_solve_pool(p, k: int, eps: float, ell: float, fresh_final: bool = False,
     _check(lib().imm_solve_pool(p, k, eps, ell, int(fresh_final), _stream(stream), _ptr(seeds),
                                 ctypes.byref(info)))
     return seeds, info.as_dict()
+
+
+def imm_server_create(g, seed_ic: int, seed_lt: int, hbm_budget_bytes: int, max_active: int):
+    out = ctypes.c_void_p()
+    _check(lib().imm_server_create(g, seed_ic, seed_lt, hbm_budget_bytes, max_active,
+                                   ctypes.byref(out)))
+    return out
+
+
+def imm_server_submit(srv, k: int, eps: float, ell: float, model: int,
+                      fresh_final: bool = False) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().imm_server_submit(srv, k, eps, ell, model, int(fresh_final), ctypes.byref(t)))
+    return t.value
+
+
+def imm_server_poll(srv, ticket: int, k: int):
+    """(done, seeds, info) -- seeds/info are None until the query has finished."""
+    seeds = np.zeros(k, dtype=np.int32)
+    info = ImmInfo()
+    done = ctypes.c_int32()
+    _check(lib().imm_server_poll(srv, ticket, _ptr(seeds), ctypes.byref(info), ctypes.byref(done)))
+    return (True, seeds, info.as_dict()) if done.value else (False, None, None)
+
+
+def imm_server_wait(srv, ticket: int, k: int, timeout_s: float = 0.0):
+    seeds = np.zeros(k, dtype=np.int32)
+    info = ImmInfo()
+    _check(lib().imm_server_wait(srv, ticket, timeout_s, _ptr(seeds), ctypes.byref(info)))
+    return seeds, info.as_dict()
+
+
+def imm_server_stats_get(srv) -> dict:
+    st = ImmServerStats()
+    _check(lib().imm_server_stats_get(srv, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def imm_server_destroy(srv) -> None:
+    _check(lib().imm_server_destroy(srv))
 
 
 def imm_log_binom(n: int, k: int) -> float:
