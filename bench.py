@@ -107,12 +107,152 @@ def cpu_baseline(w, seconds: float) -> dict:
                       f"greedy k={w.k} over them ({t_sel:.1f} s), {threads} threads"}
 
 
+# ---------------------------------------------------------------------------------------
+# Batched workload: 256 independent R-MAT instances, batched vs one at a time
+# ---------------------------------------------------------------------------------------
+def _build_instance(spec):
+    from synth import configs
+    w = configs.c4_instance(spec)
+    return spec.index, w.graph.n, w.graph.in_off, w.graph.in_src
+
+
+def build_c4(count: int, workers: int):
+    """The instances of the 256-instance mix (graphs built in worker processes, forked
+    before anything touches the GPU)."""
+    import multiprocessing as mp
+    from synth import configs, graphs
+    specs = configs.c4_specs()[:count]
+    ctx = mp.get_context("fork")
+    out = {}
+    with ctx.Pool(workers) as pool:
+        for idx, n, in_off, in_src in pool.imap_unordered(_build_instance, specs):
+            out[idx] = (n, in_off, in_src)
+            if len(out) % 32 == 0:
+                log(f"  built {len(out)}/{len(specs)} graphs")
+    res = []
+    for s in specs:
+        n, in_off, in_src = out.pop(s.index)
+        g = graphs.Graph(n, in_off, in_src, name=f"c4-{s.index}", meta=dict(kind="rmat"))
+        res.append((s, g, graphs.weighted_cascade(g)))
+    return res
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_batch(args) -> int:
+    import numpy as np
+    import paper_2009_07325_amd as imm
+    t = time.perf_counter()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    inst = build_c4(args.instances, workers)
+    m_total = sum(g.m for _, g, _ in inst)
+    log(f"{len(inst)} instances, {m_total} edges, built in {time.perf_counter() - t:.1f}s "
+        f"({workers} workers)")
+    imm.imm_init(0)
+    ggs = []
+    for s, g, p in inst:
+        ggs.append(imm.Graph.from_arrays(g.n, g.in_off, g.in_src, ic_p=p))
+    items = [dict(graph=gg, k=s.k, eps=s.eps, ell=1.0, model=imm.IMM_IC, seed=s.pool_seed)
+             for (s, _, _), gg in zip(inst, ggs)]
+    del inst
+
+    # one at a time: each query's service time; completion times as if all were submitted
+    # together and served in order
+    def solve(it):
+        return imm.imm_solve(it["graph"].handle, it["k"], it["eps"], 1.0, imm.IMM_IC, it["seed"])
+
+    solve(items[0])                     # warm-up (first launches, allocator)
+    t0 = time.perf_counter()
+    solo = []
+    for j, it in enumerate(items):
+        solo.append(solve(it))
+        if (j + 1) % 32 == 0:
+            log(f"  sequential {j + 1}/{len(items)}: {time.perf_counter() - t0:.1f}s")
+    t_seq = time.perf_counter() - t0
+    service = [i["t_total_s"] for _, i in solo]
+    done_seq = np.cumsum(service)
+    log(f"sequential: {t_seq:.2f} s for {len(items)} solves")
+
+    for i in range(args.warmup):
+        stats = {}
+        imm.imm_batch_solve(items, stats=stats)
+        log(f"warmup {i}: {stats['t_total_s']:.2f} s, {stats['ticks']} ticks")
+    times, last, stats_all = [], None, []
+    for i in range(args.steps):
+        stats = {}
+        t1 = time.perf_counter()
+        last = imm.imm_batch_solve(items, stats=stats)
+        times.append(time.perf_counter() - t1)
+        stats_all.append(stats)
+        log(f"step {i}: {times[-1]:.3f} s, {stats['ticks']} ticks, gen {stats['t_generate_s']:.3f} s "
+            f"sel {stats['t_select_s']:.3f} s")
+    mismatched = sum(1 for (s1, i1), (s2, i2) in zip(last, solo)
+                     if not (np.array_equal(s1, s2) and i1["theta"] == i2["theta"]
+                             and i1["covered"] == i2["covered"]))
+    elapsed = sum(times)
+    done_batch = [i["t_total_s"] for _, i in last]
+    philox = sum((st["edges_examined"] - st["edges_heavy"]) / 4.0 for st in stats_all)
+    k_time = sum(st["t_rr_kernel_s"] for st in stats_all)
+    k_launch = sum(st["rr_kernel_launches"] for st in stats_all)
+    achieved = philox / k_time / 1e9 if k_time else 0.0
+    out = {
+        "metric": METRIC,
+        "value": len(items) * args.steps / elapsed,
+        "unit": "IMM queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded R-MAT graphs; no dataset)",
+        "config": {"workload": f"C4: {len(items)} R-MAT instances (n log-uniform in [1e4, 2e6], "
+                               f"avg degree log-uniform in [4, 32], m total {m_total}), WC IC, "
+                               "k ~ U{5..100}, eps in {0.5, 0.2, 0.1}, one batch per step",
+                   "instances": len(items), "edges_total": m_total},
+        "batched": {"queries_s": len(items) * args.steps / elapsed,
+                    "s_per_batch": elapsed / args.steps,
+                    "completion_p50_s": _pct(done_batch, 50),
+                    "completion_p99_s": _pct(done_batch, 99),
+                    "ticks": stats_all[-1]["ticks"],
+                    "rr_sets": stats_all[-1]["rr_sets"],
+                    "rr_sets_s": stats_all[-1]["rr_sets"] / times[-1],
+                    "t_generate_s": stats_all[-1]["t_generate_s"],
+                    "t_select_s": stats_all[-1]["t_select_s"]},
+        "sequential": {"queries_s": len(items) / t_seq, "s_total": t_seq,
+                       "service_p50_s": _pct(service, 50), "service_p99_s": _pct(service, 99),
+                       "completion_p50_s": _pct(done_seq, 50),
+                       "completion_p99_s": _pct(done_seq, 99)},
+        "speedup_vs_sequential": t_seq / (elapsed / args.steps),
+        "results_equal_sequential": mismatched == 0,
+        "roofline": {
+            "kernel": "k_ic_light",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_GPHILOX,
+            "unit": "Gphilox/s",
+            "frac": achieved / PEAK_GPHILOX,
+            "traffic": None,
+            "avg_launch_ms": k_time / max(k_launch, 1) * 1e3,
+            "philox_per_launch": philox / max(k_launch, 1),
+        },
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if mismatched == 0 else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--instances", type=int, default=256, help="c4: instances of the mix")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -123,6 +263,9 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    if args.workload == "c4":
+        log("host:", json.dumps(host_info()))
+        return bench_batch(args)
     import paper_2009_07325_amd as imm
     log("host:", json.dumps(host_info()))
     t = time.perf_counter()

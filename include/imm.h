@@ -170,6 +170,47 @@ imm_status imm_solve(const imm_graph* g, int32_t k, double eps, double ell, imm_
 imm_status imm_solve_pool(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh_final,
                           void* stream, int32_t* seeds_out, imm_info* info);
 
+/* ---- batched solves (many independent instances in shared launches) ---------------------
+ * Solves every item as imm_solve(graph, k, eps, ell, model, {seed, fresh_final}) would, with
+ * bit-identical seeds and info counters (theta, LB, covered, phases, num_rr).  The
+ * instances advance together: each step generates the RR sets of every unfinished instance
+ * in one launch per model and runs all their greedy selections in one cooperative launch
+ * (gIM Sec. I motivates solving IM many times; the batch keeps the whole device busy with
+ * instances that alone would fill a fraction of it).  The caller owns the items and their
+ * seeds_out arrays (int32[k] each, host memory).  Graphs must be on the current device.
+ * Arguments are validated before any work (IMM_EINVAL names the item).  On a device or
+ * memory error the call returns it and sets status of every unfinished item.
+ * info.t_total_s is the time from the call's start to the item's completion. */
+typedef struct {
+    const imm_graph* graph;
+    int32_t k;
+    imm_model model;
+    double eps, ell;
+    uint64_t seed;          /* Philox key of the instance's RR pool */
+    int32_t fresh_final;
+    imm_status status;      /* out */
+    int32_t* seeds_out;     /* out: int32[k] in selection order */
+    imm_info info;          /* out */
+} imm_batch_item;
+
+/* Whole-batch figures (stats may be NULL): ticks (generation + selection steps), wall
+ * time in generation and selection, and the summed durations of the generation launches
+ * (HIP events), as in imm_info. */
+typedef struct {
+    int64_t ticks;
+    int64_t rr_sets;            /* RR sets generated over all items */
+    int64_t edges_examined;
+    int64_t edges_heavy;
+    double t_generate_s, t_select_s, t_total_s;
+    double t_rr_kernel_s;
+    int64_t rr_kernel_launches;
+    double t_rr_heavy_s;
+    int64_t rr_heavy_launches;
+} imm_batch_stats;
+
+imm_status imm_batch_solve(imm_batch_item* items, int32_t count, void* stream,
+                           imm_batch_stats* stats);
+
 /* ---- serving (continuous batching over one resident graph) -----------------------------
  * A server keeps the graph and one RR pool per model (IC with seed_ic, LT with seed_lt;
  * a model is served when the graph has its encoding) resident in HBM.  Queries are

@@ -28,7 +28,8 @@ EXPORTS = ("imm_init", "imm_last_error", "imm_graph_create", "imm_graph_destroy"
            "imm_graph_info", "imm_graph_export_encoding", "imm_pool_create", "imm_pool_destroy",
            "imm_pool_size", "imm_generate_rr", "imm_rr_export", "imm_rr_histogram",
            "imm_select_seeds", "imm_solve", "imm_solve_pool", "imm_log_binom",
-           "imm_lambda_prime", "imm_lambda_star", "imm_server_create", "imm_server_submit",
+           "imm_lambda_prime", "imm_lambda_star", "imm_batch_solve", "imm_server_create",
+           "imm_server_submit",
            "imm_server_poll", "imm_server_wait", "imm_server_stats_get", "imm_server_destroy")
 
 
@@ -57,6 +58,25 @@ class ImmInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class ImmBatchItem(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("k", ctypes.c_int32), ("model", ctypes.c_int),
+                ("eps", ctypes.c_double), ("ell", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("fresh_final", ctypes.c_int32), ("status", ctypes.c_int),
+                ("seeds_out", ctypes.c_void_p), ("info", ImmInfo)]
+
+
+class ImmBatchStats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("rr_sets", ctypes.c_int64),
+                ("edges_examined", ctypes.c_int64), ("edges_heavy", ctypes.c_int64),
+                ("t_generate_s", ctypes.c_double), ("t_select_s", ctypes.c_double),
+                ("t_total_s", ctypes.c_double), ("t_rr_kernel_s", ctypes.c_double),
+                ("rr_kernel_launches", ctypes.c_int64), ("t_rr_heavy_s", ctypes.c_double),
+                ("rr_heavy_launches", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class ImmServerStats(ctypes.Structure):
@@ -102,6 +122,8 @@ def lib() -> ctypes.CDLL:
             "imm_solve": [p, i32, dbl, dbl, ctypes.c_int, ctypes.POINTER(ImmOptions), p,
                           ctypes.POINTER(ImmInfo)],
             "imm_solve_pool": [p, i32, dbl, dbl, i32, p, p, ctypes.POINTER(ImmInfo)],
+            "imm_batch_solve": [ctypes.POINTER(ImmBatchItem), i32, p,
+                                ctypes.POINTER(ImmBatchStats)],
             "imm_server_create": [p, u64, u64, i64, i32, pp],
             "imm_server_submit": [p, i32, dbl, dbl, ctypes.c_int, i32, ctypes.POINTER(ctypes.c_uint64)],
             "imm_server_poll": [p, u64, p, ctypes.POINTER(ImmInfo), ctypes.POINTER(ctypes.c_int32)],
@@ -253,6 +275,31 @@ def imm_solve_pool(p, k: int, eps: float, ell: float, fresh_final: bool = False,
     _check(lib().imm_solve_pool(p, k, eps, ell, int(fresh_final), _stream(stream), _ptr(seeds),
                                 ctypes.byref(info)))
     return seeds, info.as_dict()
+
+
+def imm_batch_solve(items, stream=None, stats: dict | None = None) -> list[tuple[np.ndarray, dict]]:
+    """items: sequence of dicts with graph, k, eps, model, seed and optionally ell (1.0) and
+    fresh_final (False).  Returns (seeds, info) per item, in order; `stats`, if given, is
+    filled with the whole-batch figures."""
+    arr = (ImmBatchItem * len(items))()
+    seeds = []
+    for i, it in enumerate(items):
+        s = np.zeros(int(it["k"]), dtype=np.int32)
+        seeds.append(s)
+        g = it["graph"]
+        arr[i].graph = g.handle if isinstance(g, Graph) else g
+        arr[i].k = int(it["k"])
+        arr[i].model = int(it["model"])
+        arr[i].eps = float(it["eps"])
+        arr[i].ell = float(it.get("ell", 1.0))
+        arr[i].seed = int(it["seed"])
+        arr[i].fresh_final = int(bool(it.get("fresh_final", False)))
+        arr[i].seeds_out = s.ctypes.data
+    bs = ImmBatchStats()
+    _check(lib().imm_batch_solve(arr, len(items), _stream(stream), ctypes.byref(bs)))
+    if stats is not None:
+        stats.update(bs.as_dict())
+    return [(seeds[i], arr[i].info.as_dict()) for i in range(len(items))]
 
 
 def imm_server_create(g, seed_ic: int, seed_lt: int, hbm_budget_bytes: int, max_active: int):

@@ -322,43 +322,22 @@ extern "C" imm_status imm_pool_destroy(imm_pool* p) {
     dfree(p->ids);
     dfree(p->hist);
     dfree(p->ctr);
-    hfree(p->host_ctr);
-    dfree(p->heavy_list);
     dfree(p->cap_list);
     dfree(p->retry_list);
-    dfree(p->visited);
-    dfree(p->hvisited);
-    dfree(p->hlist);
+    p->gen.release();
     p->sel.release();
     p->launch.release();
-    if (p->ev0) (void)hipEventDestroy(p->ev0);
-    if (p->ev1) (void)hipEventDestroy(p->ev1);
     delete p;
     return IMM_OK;
 }
 
 static imm_status pool_init(imm_pool* p) {
     const imm_graph* g = p->g;
-    const bool lt = p->model == IMM_LT;
-    p->grid = g->cus * gen_blocks_per_cu(lt ? 2 : 0);
-    p->vis_words = ((int64_t)g->n + 31) / 32;
-    // light visited bitmaps: at most ~4 GiB (fewer resident blocks on huge graphs)
-    const int64_t vis_bytes_per_block = 4 * p->vis_words * 4;
-    const int64_t max_blocks = std::max<int64_t>(g->cus, ((int64_t)4 << 30) / vis_bytes_per_block);
-    if (p->grid > max_blocks) p->grid = (int)max_blocks;
     IMM_TRY(dalloc(&p->hist, g->n));
     IMM_TRY(dalloc(&p->ctr, 1));
-    IMM_TRY(dalloc(&p->visited, (int64_t)p->grid * 4 * p->vis_words));
     HIP_TRY(hipMemset(p->hist, 0, sizeof(uint32_t) * (size_t)g->n));
     HIP_TRY(hipMemset(p->ctr, 0, sizeof(PoolCounters)));
-    HIP_TRY(hipMemset(p->visited, 0, sizeof(uint32_t) * (size_t)(p->grid * 4 * p->vis_words)));
-    HIP_TRY(hipHostMalloc((void**)&p->host_ctr, sizeof(PoolCounters), hipHostMallocDefault));
-    memset(p->host_ctr, 0, sizeof(PoolCounters));
-    HIP_TRY(hipEventCreate(&p->ev0));
-    HIP_TRY(hipEventCreate(&p->ev1));
-    if (const char* b = getenv("IMM_LIGHT_BUDGET")) p->budget = std::max(1ll, atoll(b));
-    if (const char* b = getenv("IMM_HEAVY_BLOCK")) p->heavy_block = atoi(b) == 1024 ? 1024 : 256;
-    return IMM_OK;
+    return p->gen.init(g->device, p->model, g->cus);
 }
 
 extern "C" imm_status imm_pool_create(const imm_graph* g, imm_model model, uint64_t seed,
@@ -382,164 +361,13 @@ extern "C" imm_status imm_pool_create(const imm_graph* g, imm_model model, uint6
     return IMM_OK;
 }
 
-static imm_status read_counters(imm_pool* p, hipStream_t s) {
-    HIP_TRY(hipMemcpyAsync(p->host_ctr, p->ctr, sizeof(PoolCounters), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return IMM_OK;
-}
-
 extern "C" imm_status imm_pool_size(const imm_pool* p, int64_t* num_sets, int64_t* num_ids,
                                     int64_t* edges_examined) {
     if (!p) return fail(IMM_EINVAL, "pool is NULL");
-    PoolCounters c;
-    HIP_TRY(hipMemcpy(&c, p->ctr, sizeof c, hipMemcpyDeviceToHost));
     if (num_sets) *num_sets = p->count;
-    if (num_ids) *num_ids = (int64_t)sum64(c.placed);
-    if (edges_examined) *edges_examined = (int64_t)(sum64(c.edges) + sum64(c.hedges));
+    if (num_ids) *num_ids = (int64_t)p->sum.placed;
+    if (edges_examined) *edges_examined = (int64_t)(p->sum.edges + p->sum.hedges);
     return IMM_OK;
-}
-
-static GenArgs gen_args(imm_pool* p) {
-    const imm_graph* g = p->g;
-    GenArgs a{};
-    a.vrec = g->vrec;
-    a.src = g->src;
-    a.thr = g->thr;
-    a.cum = g->cum;
-    a.n = g->n;
-    a.k0 = (uint32_t)p->seed;
-    a.k1 = (uint32_t)(p->seed >> 32);
-    a.budget = p->budget;
-    a.heavy_list = p->heavy_list;
-    a.ids = p->ids;
-    a.cap_ids = p->cap_ids;
-    a.rr_start = p->rr_start;
-    a.rr_len = p->rr_len;
-    a.hist = p->hist;
-    a.ctr = p->ctr;
-    a.cap_list = p->cap_list;
-    a.visited = p->visited;
-    a.hvisited = p->hvisited;
-    a.vis_words = p->vis_words;
-    a.hlist = p->hlist;
-    return a;
-}
-
-static double elapsed_s(imm_pool* p) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, p->ev0, p->ev1) != hipSuccess) return 0.0;
-    return ms * 1e-3;
-}
-
-// Light launch over RR indices first + i (or list[i]), i < count.
-static imm_status run_light(imm_pool* p, int64_t first, int64_t count, const uint32_t* list,
-                            hipStream_t s) {
-    HIP_TRY(hipMemsetAsync(&p->ctr->work, 0, sizeof(unsigned long long), s));
-    HIP_TRY(hipMemsetAsync(&p->ctr->n_heavy, 0, 2 * sizeof(unsigned int), s));
-    GenArgs a = gen_args(p);
-    a.first = first;
-    a.count = count;
-    a.list = list;
-    int64_t grid = std::min<int64_t>(p->grid, (count + 3) / 4);
-    if (grid < 1) grid = 1;
-    HIP_TRY(hipEventRecord(p->ev0, s));
-    if (p->model == IMM_IC) HIP_TRY(launch_ic_light(a, (int)grid, s));
-    else HIP_TRY(launch_lt(a, false, (int)grid, s));
-    HIP_TRY(hipEventRecord(p->ev1, s));
-    IMM_TRY(read_counters(p, s));
-    p->kernel_s += elapsed_s(p);
-    p->kernel_launches += 1;
-    return IMM_OK;
-}
-
-static imm_status ensure_heavy(imm_pool* p) {
-    if (p->hlist) return IMM_OK;
-    const int64_t n = p->g->n;
-    const bool lt = p->model == IMM_LT;
-    // slots: IC one per 1024-thread workgroup, LT one per wave; lists of n entries each,
-    // bounded to ~4 GiB of lists
-    int64_t want = lt ? (int64_t)p->g->cus * gen_blocks_per_cu(3) * 4
-                      : (int64_t)p->g->cus * gen_blocks_per_cu(p->heavy_block == 1024 ? 1 : 4);
-    int64_t cap = std::max<int64_t>(4, ((int64_t)4 << 30) / (4 * n + 4 * p->vis_words));
-    int64_t slots = std::min(want, cap);
-    if (lt) slots = std::max<int64_t>(4, (slots / 4) * 4);
-    IMM_TRY(dalloc(&p->hlist, slots * n));
-    IMM_TRY(dalloc(&p->hvisited, slots * p->vis_words));
-    HIP_TRY(hipMemset(p->hvisited, 0, sizeof(uint32_t) * (size_t)(slots * p->vis_words)));
-    p->hslots = slots;
-    return IMM_OK;
-}
-
-// Heavy launch over the queue the last light launch filled.
-static imm_status run_heavy(imm_pool* p, uint32_t n_queue, hipStream_t s) {
-    IMM_TRY(ensure_heavy(p));
-    HIP_TRY(hipMemsetAsync(&p->ctr->hwork, 0, sizeof(unsigned int), s));
-    GenArgs a = gen_args(p);
-    a.queue = p->heavy_list;
-    a.n_queue = n_queue;
-    a.first = 0;
-    a.count = n_queue;
-    a.list = p->heavy_list;
-    HIP_TRY(hipEventRecord(p->ev0, s));
-    if (p->model == IMM_IC) {
-        int64_t grid = std::min<int64_t>(p->hslots, n_queue);
-        HIP_TRY(launch_ic_heavy(a, p->heavy_block, (int)std::max<int64_t>(grid, 1), s));
-    } else {
-        // LT: sets too long for the on-chip list walk with their lists in HBM
-        HIP_TRY(hipMemsetAsync(&p->ctr->work, 0, sizeof(unsigned long long), s));
-        int64_t grid = std::min<int64_t>(p->hslots / 4, ((int64_t)n_queue + 3) / 4);
-        HIP_TRY(launch_lt(a, true, (int)std::max<int64_t>(grid, 1), s));
-    }
-    HIP_TRY(hipEventRecord(p->ev1, s));
-    IMM_TRY(read_counters(p, s));
-    p->heavy_s += elapsed_s(p);
-    p->heavy_launches += 1;
-    return IMM_OK;
-}
-
-imm_status imm::pool_generate(imm_pool* p, int64_t upto, hipStream_t s) {
-    if (upto <= p->count) return IMM_OK;
-    if (upto > kMaxSets) return fail(IMM_ECAPACITY, "RR index %lld exceeds 2^31-1", (long long)upto);
-    const int64_t first = p->count, cnt = upto - first;
-    int64_t cap_sets = p->cap_sets;
-    IMM_TRY(dgrow(&p->rr_start, &cap_sets, upto, p->count, s));
-    cap_sets = p->cap_sets;
-    IMM_TRY(dgrow(&p->rr_len, &cap_sets, upto, p->count, s));
-    p->cap_sets = cap_sets;
-    if (cnt > p->cap_lists) {
-        dfree(p->heavy_list);
-        dfree(p->cap_list);
-        dfree(p->retry_list);
-        IMM_TRY(dalloc(&p->heavy_list, cnt));
-        IMM_TRY(dalloc(&p->cap_list, cnt));
-        IMM_TRY(dalloc(&p->retry_list, cnt));
-        p->cap_lists = cnt;
-    }
-    // id-buffer size from the mean set size seen so far, with room for the per-wave
-    // reservation chunks left partly unused at the end of each launch
-    const unsigned long long placed = sum64(p->host_ctr->placed);
-    const double mean = p->count > 0 ? (double)placed / (double)p->count : 16.0;
-    const int64_t slack = ((int64_t)p->grid * 4 + p->g->cus * 8) * (int64_t)2048;
-    const int64_t need = (int64_t)p->host_ctr->tail + (int64_t)(mean * 1.3 * (double)cnt) + slack;
-    IMM_TRY(dgrow(&p->ids, &p->cap_ids, need, (int64_t)p->host_ctr->tail, s));
-
-    IMM_TRY(run_light(p, first, cnt, nullptr, s));
-    for (int guard = 0; guard < 64; ++guard) {
-        if (p->host_ctr->n_heavy > 0) IMM_TRY(run_heavy(p, p->host_ctr->n_heavy, s));
-        const unsigned int n_cap = p->host_ctr->n_capacity;
-        if (n_cap == 0) {
-            p->count = upto;
-            return IMM_OK;
-        }
-        // grow the id buffer and rerun the sets that did not fit
-        const int64_t tail = (int64_t)p->host_ctr->tail;
-        const int64_t want = tail + (int64_t)(std::max(mean, 64.0) * 2.0 * (double)n_cap) + slack;
-        IMM_TRY(dgrow(&p->ids, &p->cap_ids, std::max(want, 2 * p->cap_ids), tail, s));
-        HIP_TRY(hipMemcpyAsync(p->retry_list, p->cap_list, sizeof(uint32_t) * n_cap,
-                               hipMemcpyDeviceToDevice, s));
-        IMM_TRY(run_light(p, 0, n_cap, p->retry_list, s));
-    }
-    return fail(IMM_EDEVICE, "RR placement did not converge");
 }
 
 extern "C" imm_status imm_generate_rr(imm_pool* p, int64_t upto, void* stream) {
@@ -652,8 +480,8 @@ void SelectLaunch::release() {
 }
 
 int64_t imm_pool::bytes() const {
-    int64_t b = cap_sets * 12 + cap_ids * 4 + (int64_t)g->n * 4 + cap_lists * 12;
-    b += (int64_t)grid * 4 * vis_words * 4 + hslots * (vis_words * 4 + (int64_t)g->n * 4);
+    int64_t b = cap_sets * 12 + cap_ids * 4 + (int64_t)g->n * 4 + cap_lists * 8;
+    b += gen.bytes();
     return b + sel.bytes();
 }
 
@@ -668,7 +496,7 @@ static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t
         IMM_TRY(dalloc(&w->n_covered, 1));
         HIP_TRY(hipHostMalloc((void**)&w->host_cov, sizeof(unsigned long long), hipHostMallocDefault));
     }
-    const int64_t members = (int64_t)sum64(p->host_ctr->placed);
+    const int64_t members = (int64_t)p->sum.placed;
     if (members > w->cap_inv) {
         dfree(w->inv);
         int64_t c = members + members / 4 + 1024;
@@ -736,11 +564,18 @@ imm_status imm::select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* 
         HIP_TRY(hipHostMalloc((void**)&L->host_bar, sizeof(GridBarrier), hipHostMallocDefault));
         L->cap = ninst;
     }
-    int32_t maxk = 0;
-    for (int32_t i = 0; i < ninst; ++i) maxk = std::max(maxk, inst[i].k);
     HIP_TRY(hipMemcpyAsync(L->d_inst, inst, sizeof(SelInst) * (size_t)ninst, hipMemcpyHostToDevice, s));
+    // one cooperative launch per group of at most select_max_inst() instances; the barrier
+    // counters start from zero for each launch, and its error flag is collected at the end
+    const int32_t per = select_max_inst();
     HIP_TRY(hipMemsetAsync(L->bar, 0, sizeof(GridBarrier), s));
-    HIP_TRY(launch_select_coop(L->d_inst, ninst, maxk, L->bar, s));
+    for (int32_t a = 0; a < ninst; a += per) {
+        const int32_t cnt = std::min(per, ninst - a);
+        int32_t maxk = 0;
+        for (int32_t i = a; i < a + cnt; ++i) maxk = std::max(maxk, inst[i].k);
+        if (a > 0) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(L->bar), 16 * 16 + 1, 0u, s));
+        HIP_TRY(launch_select_coop(L->d_inst + a, cnt, maxk, L->bar, s));
+    }
     HIP_TRY(hipMemcpyAsync(L->host_bar, L->bar, sizeof(GridBarrier), hipMemcpyDeviceToHost, s));
     for (int32_t i = 0; i < ninst; ++i) {
         SelectWs* w = ws[i];
@@ -781,8 +616,8 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
     if (!seeds_out) return fail(IMM_EINVAL, "seeds_out is NULL");
     const double t0 = now_s();
     double t_gen = 0.0, t_sel = 0.0;
-    const double kernel_s0 = p->kernel_s, heavy_s0 = p->heavy_s;
-    const int64_t launches0 = p->kernel_launches, heavy0 = p->heavy_launches;
+    const double kernel_s0 = p->gen.kernel_s, heavy_s0 = p->gen.heavy_s;
+    const int64_t launches0 = p->gen.kernel_launches, heavy0 = p->gen.heavy_launches;
     ImmPlan plan;
     IMM_TRY(plan.init(p->g->n, k, eps, ell, fresh));
     while (!plan.done) {
@@ -801,9 +636,9 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
         info->theta = plan.theta;
         info->num_rr = plan.upto;
         info->covered = plan.covered;
-        info->edges_examined = (int64_t)(sum64(p->host_ctr->edges) + sum64(p->host_ctr->hedges));
-        info->edges_heavy = (int64_t)sum64(p->host_ctr->hedges);
-        info->pool_ids = (int64_t)sum64(p->host_ctr->placed);
+        info->edges_examined = (int64_t)(p->sum.edges + p->sum.hedges);
+        info->edges_heavy = (int64_t)p->sum.hedges;
+        info->pool_ids = (int64_t)p->sum.placed;
         info->phases = plan.phases;
         info->lb = plan.lb;
         info->spread_est = plan.spread_est();
@@ -812,10 +647,10 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
         info->t_generate_s = t_gen;
         info->t_select_s = t_sel;
         info->t_total_s = now_s() - t0;
-        info->t_rr_kernel_s = p->kernel_s - kernel_s0;
-        info->rr_kernel_launches = p->kernel_launches - launches0;
-        info->t_rr_heavy_s = p->heavy_s - heavy_s0;
-        info->rr_heavy_launches = p->heavy_launches - heavy0;
+        info->t_rr_kernel_s = p->gen.kernel_s - kernel_s0;
+        info->rr_kernel_launches = p->gen.kernel_launches - launches0;
+        info->t_rr_heavy_s = p->gen.heavy_s - heavy_s0;
+        info->rr_heavy_launches = p->gen.heavy_launches - heavy0;
     }
     return IMM_OK;
 }

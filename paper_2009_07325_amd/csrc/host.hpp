@@ -179,6 +179,46 @@ struct SelectLaunch {
     void release();
 };
 
+// Launch state and scratch of RR-generation launches of one model over one or more pools
+// (a plain pool owns one; a batch shares one across its instances).
+struct GenCtx {
+    int device = 0;
+    imm_model model = IMM_IC;
+    int cus = 0;
+    int grid = 0;                       // light launch: blocks of 256 threads
+    int64_t vis_n = 0;                  // vertices the bitmaps cover (largest graph seen)
+    int64_t vis_words = 0;
+    uint32_t* visited = nullptr;        // grid * 4 light bitmaps
+    int64_t hslots = 0;                 // heavy slots (IC: workgroups, LT: waves)
+    uint32_t* hvisited = nullptr;
+    int32_t* hlist = nullptr;           // hslots lists of vis_n entries
+    int64_t budget = 4096;              // light-wave group budget per set
+    int heavy_block = 256;              // threads per heavy set (256 or 1024)
+
+    LaunchCounters* lc = nullptr;
+    LaunchCounters* host_lc = nullptr;  // pinned
+    int64_t cap_queue = 0;
+    unsigned long long* queue = nullptr;  // light -> heavy queue
+    int64_t cap_inst = 0;
+    GenInst* d_inst = nullptr;
+    GenInst* host_inst = nullptr;       // pinned
+    int64_t* d_work_off = nullptr;
+    int64_t* host_work_off = nullptr;   // pinned
+    PoolSummary* d_sum = nullptr;
+    PoolSummary* host_sum = nullptr;    // pinned
+
+    // HIP events bracketing the light and heavy launches
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    double kernel_s = 0.0;              // light kernel (IC) / walk kernel (LT)
+    int64_t kernel_launches = 0;
+    double heavy_s = 0.0;               // heavy kernel (IC) / HBM-list walk kernel (LT)
+    int64_t heavy_launches = 0;
+
+    imm_status init(int device_, imm_model model_, int cus_);
+    int64_t bytes() const;
+    void release();
+};
+
 }  // namespace imm
 
 struct imm_pool {
@@ -194,37 +234,25 @@ struct imm_pool {
     int32_t* ids = nullptr;
     uint32_t* hist = nullptr;
     imm::PoolCounters* ctr = nullptr;
-    imm::PoolCounters* host_ctr = nullptr;   // pinned mirror
+    imm::PoolSummary sum{};              // host copy, current after every generation call
 
     int64_t cap_lists = 0;
-    uint32_t* heavy_list = nullptr;     // light -> heavy queue
     uint32_t* cap_list = nullptr;       // id-buffer capacity misses
     uint32_t* retry_list = nullptr;
 
-    int grid = 0;                       // light launch: blocks of 256 threads
-    int64_t vis_words = 0;
-    uint32_t* visited = nullptr;        // grid * 4 bitmaps
-    int64_t hslots = 0;                 // heavy slots (IC: workgroups, LT: waves)
-    uint32_t* hvisited = nullptr;
-    int32_t* hlist = nullptr;
-    int64_t budget = 4096;              // light-wave group budget per set
-    int heavy_block = 256;              // threads per heavy set (256 or 1024)
-
+    imm::GenCtx gen;                    // generation scratch of this pool's own calls
     imm::SelectWs sel;                  // selection workspace of imm_select_seeds / solve
     imm::SelectLaunch launch;
-
-    // HIP events bracketing each RR-generation kernel launch
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double kernel_s = 0.0;               // light kernel (IC) / walk kernel (LT)
-    int64_t kernel_launches = 0;
-    double heavy_s = 0.0;                // heavy kernel (IC) / HBM-list walk kernel (LT)
-    int64_t heavy_launches = 0;
 
     int64_t bytes() const;               // device memory held
 };
 
 namespace imm {
 
+// Extends each pools[i] to upto[i] sets (no-op where it already holds that many) with
+// shared light / heavy launches.  All pools must have the context's model.
+imm_status gen_run(GenCtx* c, imm_pool* const* pools, const int64_t* upto, int32_t count,
+                   hipStream_t s);
 imm_status pool_generate(imm_pool* p, int64_t upto, hipStream_t s);
 imm_status check_range(const imm_pool* p, int64_t first, int64_t count);
 

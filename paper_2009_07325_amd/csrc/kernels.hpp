@@ -12,15 +12,30 @@ namespace imm {
 // updates once per launch are spread over 64 slots (index = wave slot & 63).
 struct alignas(64) PoolCounters {
     unsigned long long tail;       // next free entry of the id buffer (chunk reservations)
-    unsigned long long work;       // work-queue cursor of the current light launch
-    unsigned int hwork;            // work-queue cursor of the current heavy launch
-    unsigned int n_heavy;          // sets queued for the heavy kernel by the light launch
-    unsigned int n_capacity;       // sets that found the id buffer full
-    unsigned int pad[9];
+    unsigned int n_capacity;       // sets that found the id buffer full (this launch)
+    unsigned int pad[13];
     unsigned long long placed[64]; // members written
     unsigned long long edges[64];  // in-edges examined by sets placed by the light kernel
     unsigned long long hedges[64]; // ... by the heavy kernel
 };
+
+// Counters of one generation launch (light + heavy), zeroed before the light launch.
+struct alignas(64) LaunchCounters {
+    unsigned long long work;       // light work-queue cursor
+    unsigned int hwork;            // heavy work-queue cursor
+    unsigned int n_heavy;          // sets the light launch queued for the heavy launch
+    unsigned int pad[12];
+};
+
+// Host-bound summary of one pool's counters, written by launch_pool_summary.
+struct PoolSummary {
+    unsigned long long tail, placed, edges, hedges;
+    unsigned int n_capacity;       // read and then cleared for the next launch
+    unsigned int pad;
+};
+
+constexpr int kGenFetch = 8;       // RR indices a light wave takes per work-counter fetch
+constexpr int kGenIdChunk = 1024;  // id-buffer entries a light wave reserves at a time
 
 // ---- graph.hip ----------------------------------------------------------------------
 // Checks the CSR and weights; sets bits of *err: 1 offsets, 2 sources, 4 IC p, 8 LT w.
@@ -35,24 +50,20 @@ hipError_t launch_encode_lt(int32_t n, const int64_t* in_off, const uint32_t* w,
                             hipStream_t s);
 
 // ---- rr_gen.hip ---------------------------------------------------------------------
-struct GenArgs {
+// One (graph, pool) of a generation launch.  A launch covers any number of instances:
+// its work items are the concatenation of every instance's RR indices.
+struct GenInst {
     // graph
     const VRec* vrec;
     const int32_t* src;
     const uint32_t* thr;     // IC per-edge thresholds (padded to a multiple of 4 edges)
     const uint32_t* cum;     // LT cumulative thresholds
     int32_t n;
-    uint32_t k0, k1;         // Philox key
-    // light launch: RR indices first + i for i in [0, count), or list[i] when list is set
+    uint32_t k0, k1;         // Philox key (pool seed)
+    // RR indices of this launch: first + j, or list[j], for j in [0, count)
     int64_t first;
-    int64_t count;
     const uint32_t* list;
-    int64_t budget;          // 4-edge groups a light wave may examine for one set
-    uint32_t* heavy_list;    // light -> heavy queue
-    // heavy launch: queue[0 .. n_queue)
-    const uint32_t* queue;
-    uint32_t n_queue;
-    // outputs
+    // pool outputs
     int32_t* ids;
     int64_t cap_ids;
     int64_t* rr_start;
@@ -60,17 +71,36 @@ struct GenArgs {
     uint32_t* hist;
     PoolCounters* ctr;
     uint32_t* cap_list;      // RR indices that found the id buffer full
-    // scratch
-    uint32_t* visited;       // light: one n-bit bitmap per wave slot
-    uint32_t* hvisited;      // heavy: one n-bit bitmap per heavy slot
-    int64_t vis_words;       // words per bitmap
-    int32_t* hlist;          // heavy: one n-entry member list per heavy slot
 };
 
-hipError_t launch_ic_light(const GenArgs& a, int grid, hipStream_t s);   // 256-thread blocks
-hipError_t launch_ic_heavy(const GenArgs& a, int block, int grid, hipStream_t s);  // 256 or 1024
-hipError_t launch_lt(const GenArgs& a, bool big, int grid, hipStream_t s);
+struct GenLaunch {
+    const GenInst* inst;     // device array
+    int32_t ninst;
+    const int64_t* work_off; // device array [ninst + 1]: work items of instance i are
+                             // [work_off[i], work_off[i+1])
+    int64_t total;           // work_off[ninst]
+    int64_t budget;          // 4-edge groups a light wave may examine for one set
+    LaunchCounters* lc;
+    unsigned long long* heavy_list;  // light -> heavy queue: instance << 32 | RR index
+    uint32_t n_queue;        // IC heavy launch: entries of heavy_list to process
+    // LT walk over HBM lists: when set, the work items are heavy_in[0, total) (entries as
+    // in heavy_list) instead of the instances' RR ranges
+    const unsigned long long* heavy_in;
+    // scratch, sized for the largest instance
+    uint32_t* visited;       // light: one bitmap of vis_words words per wave slot
+    uint32_t* hvisited;      // heavy: one bitmap per heavy slot
+    int64_t vis_words;
+    int32_t* hlist;          // heavy: one member list of list_stride entries per heavy slot
+    int64_t list_stride;
+};
+
+hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s);   // 256-thread blocks
+hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s);  // 256 or 1024
+hipError_t launch_lt(const GenLaunch& a, bool big, int grid, hipStream_t s);
 int rr_light_capacity();
+// Sums each instance's spread counters into out[i] and clears its n_capacity.
+hipError_t launch_pool_summary(const GenInst* inst, int32_t ninst, PoolSummary* out,
+                               hipStream_t s);
 // occupancy in blocks per CU: 0 IC light, 1 IC heavy (1024), 2 LT, 3 LT with HBM lists,
 // 4 IC heavy (256)
 int gen_blocks_per_cu(int which);
@@ -123,6 +153,7 @@ struct alignas(64) GridBarrier {
     unsigned int pad[14];
 };
 int select_coop_grid();            // blocks of the cooperative launch (co-resident)
+int select_max_inst();             // instances one cooperative launch can take
 hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
                               hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);

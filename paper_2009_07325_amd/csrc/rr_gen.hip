@@ -32,8 +32,8 @@ namespace imm {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLightCap = 1024;    // members a light set may hold on chip
-constexpr int kFetch = 8;          // RR indices per work-counter fetch
-constexpr int kIdChunk = 1024;     // id-buffer entries reserved per wave at a time
+constexpr int kFetch = kGenFetch;
+constexpr int kIdChunk = kGenIdChunk;
 
 int rr_light_capacity() { return kLightCap; }
 
@@ -52,64 +52,109 @@ __device__ __forceinline__ bool vis_test_and_set(uint32_t* vis, int32_t v) {
 // Orders the visited-bitmap clears of one set before the next set's test-and-sets.
 __device__ __forceinline__ void vis_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
-__device__ __forceinline__ uint32_t set_index(const GenArgs& a, int64_t i) {
-    return a.list ? a.list[i] : (uint32_t)(a.first + i);
-}
-
 // Wave-private state kept in (uniform) registers.
 struct WaveState {
-    int64_t cur = 0, end = 0;                // fetched index range [cur, end)
-    unsigned long long chunk_base = 0;       // reserved id-buffer chunk
-    int64_t chunk_left = 0;
+    int64_t cur = 0;                         // next fetched work item
+    int32_t left = 0;                        // fetched work items not yet taken
+    int32_t inst = -1;                       // instance of the current set
+    int64_t inst_lo = 0, inst_hi = 0;        // its work items [inst_lo, inst_hi)
+    int32_t place_inst = -1;                 // instance of the reserved chunk and counters
+    int32_t chunk_left = 0;
+    unsigned long long chunk_base = 0;
     unsigned long long placed = 0, edges = 0;
-    uint32_t heavy_buf = 0;                  // lane i holds the i-th queued RR index
-    int heavy_n = 0;
+    unsigned long long heavy_buf = 0;        // lane i holds the i-th queued (instance, r)
+    int32_t heavy_n = 0;
 };
 
-__device__ __forceinline__ bool next_set(const GenArgs& a, WaveState& ws, uint32_t& r) {
-    if (ws.cur >= ws.end) {
-        unsigned long long i = 0;
-        if (lane_id() == 0) i = atomic_add_agent(&a.ctr->work, (unsigned long long)kFetch);
-        i = uniform64(i);
-        if ((int64_t)i >= a.count) return false;
-        ws.cur = (int64_t)i;
-        ws.end = min((int64_t)i + kFetch, a.count);
+// Find the instance of work item w: largest i with work_off[i] <= w.
+__device__ __forceinline__ int32_t find_inst(const GenLaunch& L, int64_t w) {
+    int32_t lo = 0, hi = L.ninst;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (L.work_off[mid] <= w) lo = mid; else hi = mid;
     }
-    r = uniform(set_index(a, ws.cur));
-    ++ws.cur;
+    return lo;
+}
+
+__device__ __forceinline__ void flush_counters(const GenLaunch& L, WaveState& ws, int64_t slot) {
+    if (ws.place_inst >= 0 && lane_id() == 0) {
+        PoolCounters* c = L.inst[ws.place_inst].ctr;
+        if (ws.placed) atomic_add_agent(&c->placed[slot & 63], ws.placed);
+        if (ws.edges)
+            atomic_add_agent(L.heavy_in ? &c->hedges[slot & 63] : &c->edges[slot & 63], ws.edges);
+    }
+    ws.placed = 0;
+    ws.edges = 0;
+}
+
+// Next set of the launch: its instance (uniform) and RR index.  False when the launch's
+// work is exhausted.
+__device__ __forceinline__ bool next_set(const GenLaunch& L, WaveState& ws, int32_t& inst,
+                                         uint32_t& r) {
+    if (ws.left == 0) {
+        unsigned long long i = 0;
+        if (lane_id() == 0) i = atomic_add_agent(&L.lc->work, (unsigned long long)kFetch);
+        i = uniform64(i);
+        if ((int64_t)i >= L.total) return false;
+        ws.cur = (int64_t)i;
+        ws.left = (int32_t)min((int64_t)kFetch, L.total - (int64_t)i);
+    }
+    const int64_t w = ws.cur++;
+    --ws.left;
+    if (L.heavy_in) {
+        const unsigned long long e = uniform64(L.heavy_in[w]);
+        inst = (int32_t)(e >> 32);
+        r = (uint32_t)e;
+        return true;
+    }
+    if (ws.inst < 0 || w < ws.inst_lo || w >= ws.inst_hi) {
+        ws.inst = uniform(find_inst(L, w));
+        ws.inst_lo = (int64_t)uniform64((uint64_t)L.work_off[ws.inst]);
+        ws.inst_hi = (int64_t)uniform64((uint64_t)L.work_off[ws.inst + 1]);
+    }
+    inst = ws.inst;
+    const GenInst& I = L.inst[inst];
+    const int64_t j = w - ws.inst_lo;
+    r = uniform(I.list ? I.list[j] : (uint32_t)(I.first + j));
     return true;
 }
 
-__device__ __forceinline__ void flush_heavy(const GenArgs& a, WaveState& ws) {
+__device__ __forceinline__ void flush_heavy(const GenLaunch& L, WaveState& ws) {
     if (ws.heavy_n == 0) return;
     unsigned int at = 0;
-    if (lane_id() == 0) at = atomic_add_agent(&a.ctr->n_heavy, (unsigned int)ws.heavy_n);
+    if (lane_id() == 0) at = atomic_add_agent(&L.lc->n_heavy, (unsigned int)ws.heavy_n);
     at = uniform(at);
-    if (lane_id() < ws.heavy_n) a.heavy_list[at + lane_id()] = ws.heavy_buf;
+    if (lane_id() < ws.heavy_n) L.heavy_list[at + lane_id()] = ws.heavy_buf;
     ws.heavy_n = 0;
 }
 
-__device__ __forceinline__ void push_heavy(const GenArgs& a, WaveState& ws, uint32_t r) {
-    if (lane_id() == ws.heavy_n) ws.heavy_buf = r;
-    if (++ws.heavy_n == kWave) flush_heavy(a, ws);
+__device__ __forceinline__ void push_heavy(const GenLaunch& L, WaveState& ws, int32_t inst, uint32_t r) {
+    if (lane_id() == ws.heavy_n) ws.heavy_buf = ((unsigned long long)(uint32_t)inst << 32) | r;
+    if (++ws.heavy_n == kWave) flush_heavy(L, ws);
 }
 
-__device__ __forceinline__ void push_capacity_miss(const GenArgs& a, uint32_t r) {
-    const unsigned int at = atomic_add_agent(&a.ctr->n_capacity, 1u);
-    a.cap_list[at] = r;
+__device__ __forceinline__ void push_capacity_miss(const GenInst& I, uint32_t r) {
+    const unsigned int at = atomic_add_agent(&I.ctr->n_capacity, 1u);
+    I.cap_list[at] = r;
 }
 
-// Write a finished set (members list[0..size)) into the id buffer; wave-cooperative.
-__device__ void place_wave(const GenArgs& a, WaveState& ws, uint32_t r, const int32_t* list,
-                           int32_t size, uint64_t examined) {
+// Write a finished set (members list[0..size)) into its pool; wave-cooperative.
+__device__ void place_wave(const GenLaunch& L, WaveState& ws, int64_t slot, int32_t inst,
+                           uint32_t r, const int32_t* list, int32_t size, uint64_t examined) {
     const int lane = lane_id();
+    const GenInst& I = L.inst[inst];
+    if (ws.place_inst != inst) {
+        flush_counters(L, ws, slot);
+        ws.place_inst = inst;
+        ws.chunk_left = 0;
+    }
     if (ws.chunk_left < size) {
-        const int64_t want = max((int64_t)kIdChunk, (int64_t)size);
+        const int32_t want = max(kIdChunk, size);
         unsigned long long base = 0;
-        if (lane == 0) base = atomic_add_agent(&a.ctr->tail, (unsigned long long)want);
+        if (lane == 0) base = atomic_add_agent(&I.ctr->tail, (unsigned long long)want);
         base = uniform64(base);
-        if ((int64_t)base + want > a.cap_ids) {
-            if (lane == 0) push_capacity_miss(a, r);
+        if ((int64_t)base + want > I.cap_ids) {
+            if (lane == 0) push_capacity_miss(I, r);
             ws.chunk_left = 0;
             return;
         }
@@ -118,12 +163,12 @@ __device__ void place_wave(const GenArgs& a, WaveState& ws, uint32_t r, const in
     }
     for (int32_t i = lane; i < size; i += kWave) {
         const int32_t v = list[i];
-        a.ids[ws.chunk_base + i] = v;
-        __hip_atomic_fetch_add(a.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        I.ids[ws.chunk_base + i] = v;
+        __hip_atomic_fetch_add(I.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
-        a.rr_start[r] = (int64_t)ws.chunk_base;
-        a.rr_len[r] = size;
+        I.rr_start[r] = (int64_t)ws.chunk_base;
+        I.rr_len[r] = size;
     }
     ws.chunk_base += (unsigned long long)size;
     ws.chunk_left -= size;
@@ -131,12 +176,9 @@ __device__ void place_wave(const GenArgs& a, WaveState& ws, uint32_t r, const in
     ws.edges += examined;
 }
 
-__device__ __forceinline__ void wave_exit(const GenArgs& a, WaveState& ws, int64_t slot) {
-    flush_heavy(a, ws);
-    if (lane_id() == 0) {
-        if (ws.placed) atomic_add_agent(&a.ctr->placed[slot & 63], ws.placed);
-        if (ws.edges) atomic_add_agent(&a.ctr->edges[slot & 63], ws.edges);
-    }
+__device__ __forceinline__ void wave_exit(const GenLaunch& L, WaveState& ws, int64_t slot) {
+    flush_heavy(L, ws);
+    flush_counters(L, ws, slot);
 }
 
 // ------------------------------------------------------------------------------------
@@ -147,9 +189,26 @@ __device__ __forceinline__ void wave_exit(const GenArgs& a, WaveState& ws, int64
 // together and each lane finds its vertex by a search over the batch's group prefix.
 constexpr int32_t kBigGroups = 48;
 
+// The graph fields a set's traversal reads, loaded once per set into registers.
+struct GraphView {
+    const VRec* vrec;
+    const int32_t* src;
+    const uint32_t* w;       // IC thresholds or LT cumulative thresholds
+    uint32_t k0, k1;
+    int32_t n;
+};
+
+__device__ __forceinline__ GraphView ic_view(const GenInst& I) {
+    return GraphView{I.vrec, I.src, I.thr, I.k0, I.k1, I.n};
+}
+
+__device__ __forceinline__ GraphView lt_view(const GenInst& I) {
+    return GraphView{I.vrec, I.src, I.cum, I.k0, I.k1, I.n};
+}
+
 // Tests the in-edges of group g that lie in [s, e_end) for set r.  Live edges whose source
 // is newly visited are returned in w[] with fresh[] set.
-__device__ __forceinline__ void test_group(const GenArgs& a, uint32_t r, uint32_t g, uint32_t s,
+__device__ __forceinline__ void test_group(const GraphView& a, uint32_t r, uint32_t g, uint32_t s,
                                            uint32_t e_end, bool uniform_thr, uint32_t uthr,
                                            uint32_t* vis, int32_t w[4], bool fresh[4]) {
     const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, a.k0, a.k1);
@@ -157,7 +216,7 @@ __device__ __forceinline__ void test_group(const GenArgs& a, uint32_t r, uint32_
     if (uniform_thr) {
         t[0] = t[1] = t[2] = t[3] = uthr;
     } else {
-        const uint4 tv = *reinterpret_cast<const uint4*>(a.thr + ((int64_t)g << 2));
+        const uint4 tv = *reinterpret_cast<const uint4*>(a.w + ((int64_t)g << 2));
         t[0] = tv.x; t[1] = tv.y; t[2] = tv.z; t[3] = tv.w;
     }
     const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
@@ -226,18 +285,20 @@ struct LightLds {
     int32_t list[kLightCap];
 };
 
-__global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_ic_light(GenLaunch G) {
     __shared__ LightLds lds_all[kWavesPerBlock];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     LightLds& L = lds_all[wib];
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
-    uint32_t* vis = a.visited + slot * a.vis_words;
+    uint32_t* vis = G.visited + slot * G.vis_words;
     int32_t* list = L.list;
     WaveState ws;
 
+    int32_t inst;
     uint32_t r;
-    while (next_set(a, ws, r)) {
+    while (next_set(G, ws, inst, r)) {
+        const GraphView a = ic_view(G.inst[inst]);
         const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, a.k0, a.k1);
         if (lane == 0) {
             list[0] = root;
@@ -274,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
             const int64_t total = (int64_t)wave_sum((uint64_t)ng);
             examined += wave_sum((uint64_t)dg);
             wave_sync();
-            if (used + total > a.budget) {
+            if (used + total > G.budget) {
                 abandon = true;
                 break;
             }
@@ -323,13 +384,13 @@ __global__ __launch_bounds__(kBlock) void k_ic_light(GenArgs a) {
             wave_sync();
             head += nb;
         }
-        if (abandon) push_heavy(a, ws, r);
-        else place_wave(a, ws, r, list, size, examined);
+        if (abandon) push_heavy(G, ws, inst, r);
+        else place_wave(G, ws, slot, inst, r, list, size, examined);
         for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
         vis_fence();
         wave_sync();
     }
-    wave_exit(a, ws, slot);
+    wave_exit(G, ws, slot);
 }
 
 // ------------------------------------------------------------------------------------
@@ -355,7 +416,7 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* wsum) {
 }
 
 template <int kHeavyBlock>
-__global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
+__global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenLaunch G) {
     constexpr int kHeavyWaves = kHeavyBlock / kWave;
     constexpr uint32_t kBigHeavy = kHeavyBlock / 4;
     __shared__ int32_t pre[kHeavyBlock + 1];
@@ -368,16 +429,18 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
     __shared__ unsigned long long s_base;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int64_t slot = blockIdx.x;
-    uint32_t* vis = a.hvisited + slot * a.vis_words;
-    int32_t* list = a.hlist + slot * (int64_t)a.n;
-    unsigned long long placed = 0, edges = 0;
+    uint32_t* vis = G.hvisited + slot * G.vis_words;
+    int32_t* list = G.hlist + slot * G.list_stride;
 
     for (;;) {
-        if (tid == 0) s_idx = atomic_add_agent(&a.ctr->hwork, 1u);
+        if (tid == 0) s_idx = atomic_add_agent(&G.lc->hwork, 1u);
         __syncthreads();
-        const unsigned int idx = s_idx;
-        if (idx >= a.n_queue) break;
-        const uint32_t r = a.queue[idx];
+        const unsigned int idx = uniform(s_idx);
+        if (idx >= G.n_queue) break;
+        const unsigned long long qe = uniform64(G.heavy_list[idx]);
+        const GenInst& I = G.inst[(int32_t)(qe >> 32)];
+        const GraphView a = ic_view(I);
+        const uint32_t r = (uint32_t)qe;
         if (tid == 0) {
             const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, a.k0, a.k1);
             list[0] = root;
@@ -461,15 +524,15 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
         }
         // place the set
         if (tid == 0) {
-            unsigned long long b = atomic_add_agent(&a.ctr->tail, (unsigned long long)size);
-            if ((int64_t)b + size > a.cap_ids) {
-                push_capacity_miss(a, r);
+            unsigned long long b = atomic_add_agent(&I.ctr->tail, (unsigned long long)size);
+            if ((int64_t)b + size > I.cap_ids) {
+                push_capacity_miss(I, r);
                 b = ~0ull;
             } else {
-                a.rr_start[r] = (int64_t)b;
-                a.rr_len[r] = size;
-                placed += (unsigned long long)size;
-                edges += examined;
+                I.rr_start[r] = (int64_t)b;
+                I.rr_len[r] = size;
+                atomic_add_agent(&I.ctr->placed[slot & 63], (unsigned long long)size);
+                atomic_add_agent(&I.ctr->hedges[slot & 63], (unsigned long long)examined);
             }
             s_base = b;
         }
@@ -478,17 +541,13 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
         for (int32_t i = tid; i < size; i += kHeavyBlock) {
             const int32_t v = list[i];
             if (b != ~0ull) {
-                a.ids[b + i] = v;
-                __hip_atomic_fetch_add(a.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                I.ids[b + i] = v;
+                __hip_atomic_fetch_add(I.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             vis_clear(vis, v);
         }
         vis_fence();
         __syncthreads();
-    }
-    if (tid == 0) {
-        if (placed) atomic_add_agent(&a.ctr->placed[slot & 63], placed);
-        if (edges) atomic_add_agent(&a.ctr->hedges[slot & 63], edges);
     }
 }
 
@@ -497,15 +556,15 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenArgs a) {
 // vertex: for short in-lists one coalesced load and a ballot; for long ones a 64-ary
 // search over the non-decreasing cumulative thresholds.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ bool lt_hit(const GenArgs& a, int64_t j, uint32_t x) {
-    const uint32_t c = a.cum[j];
+__device__ __forceinline__ bool lt_hit(const GraphView& a, int64_t j, uint32_t x) {
+    const uint32_t c = a.w[j];
     return c > x || c == kAlways;
 }
 
 // First j in [s, e) whose cumulative threshold is above the draw (a saturated entry always
 // qualifies), or -1.  The predicate is monotone in j because cum is non-decreasing within
 // an in-list, so a 64-ary search narrows [lo, hi) by a factor of 65 per step.
-__device__ __forceinline__ int64_t lt_pick(const GenArgs& a, int64_t s, int64_t e, uint32_t x) {
+__device__ __forceinline__ int64_t lt_pick(const GraphView& a, int64_t s, int64_t e, uint32_t x) {
     const int lane = lane_id();
     int64_t lo = s, hi = e;      // the answer lies in [lo, hi]; hi is a hit iff hi_hit
     bool hi_hit = false;
@@ -531,19 +590,21 @@ __device__ __forceinline__ int64_t lt_pick(const GenArgs& a, int64_t s, int64_t 
 }
 
 template <bool kBig>
-__global__ __launch_bounds__(kBlock) void k_rr_lt(GenArgs a) {
+__global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
     __shared__ int32_t lds_list[kWavesPerBlock][kBig ? 1 : kLightCap];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
-    uint32_t* vis = (kBig ? a.hvisited : a.visited) + slot * a.vis_words;
-    int32_t* list = kBig ? a.hlist + slot * (int64_t)a.n : lds_list[wib];
-    const int32_t cap = kBig ? a.n : kLightCap;
-    const uint32_t k0 = a.k0, k1 = a.k1;
+    uint32_t* vis = (kBig ? G.hvisited : G.visited) + slot * G.vis_words;
+    int32_t* list = kBig ? G.hlist + slot * G.list_stride : lds_list[wib];
     WaveState ws;
 
+    int32_t inst;
     uint32_t r;
-    while (next_set(a, ws, r)) {
+    while (next_set(G, ws, inst, r)) {
+        const GraphView a = lt_view(G.inst[inst]);
+        const int32_t cap = kBig ? a.n : kLightCap;
+        const uint32_t k0 = a.k0, k1 = a.k1;
         int32_t v = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
         if (lane == 0) {
             list[0] = v;
@@ -575,30 +636,30 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenArgs a) {
             v = u;
         }
         if (kBig) __threadfence(); else wave_sync();
-        if (abandon) push_heavy(a, ws, r);
-        else place_wave(a, ws, r, list, size, examined);
+        if (abandon) push_heavy(G, ws, inst, r);
+        else place_wave(G, ws, slot, inst, r, list, size, examined);
         for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
         vis_fence();
         wave_sync();
     }
-    wave_exit(a, ws, slot);
+    wave_exit(G, ws, slot);
 }
 
 // ------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------
-hipError_t launch_ic_light(const GenArgs& a, int grid, hipStream_t s) {
+hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s) {
     k_ic_light<<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_ic_heavy(const GenArgs& a, int block, int grid, hipStream_t s) {
+hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s) {
     if (block == 256) k_ic_heavy<256><<<grid, 256, 0, s>>>(a);
     else k_ic_heavy<1024><<<grid, 1024, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_lt(const GenArgs& a, bool big, int grid, hipStream_t s) {
+hipError_t launch_lt(const GenLaunch& a, bool big, int grid, hipStream_t s) {
     if (big) k_rr_lt<true><<<grid, kBlock, 0, s>>>(a);
     else k_rr_lt<false><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
@@ -616,6 +677,37 @@ int gen_blocks_per_cu(int which) {
     }
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
+}
+
+// One wave per instance.
+__global__ void k_pool_summary(const GenInst* __restrict__ inst, int32_t ninst,
+                               PoolSummary* __restrict__ out) {
+    const int lane = lane_id();
+    const int32_t i = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    if (i >= ninst) return;
+    PoolCounters* c = inst[i].ctr;
+    const unsigned long long pl = wave_sum((uint64_t)c->placed[lane]);
+    const unsigned long long ed = wave_sum((uint64_t)c->edges[lane]);
+    const unsigned long long he = wave_sum((uint64_t)c->hedges[lane]);
+    if (lane == 0) {
+        PoolSummary o;
+        o.tail = c->tail;
+        o.placed = pl;
+        o.edges = ed;
+        o.hedges = he;
+        o.n_capacity = c->n_capacity;
+        o.pad = 0;
+        out[i] = o;
+        c->n_capacity = 0u;
+    }
+}
+
+hipError_t launch_pool_summary(const GenInst* inst, int32_t ninst, PoolSummary* out,
+                               hipStream_t s) {
+    if (ninst <= 0) return hipSuccess;
+    const int blocks = (ninst + kWavesPerBlock - 1) / kWavesPerBlock;
+    k_pool_summary<<<blocks, kBlock, 0, s>>>(inst, ninst, out);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------

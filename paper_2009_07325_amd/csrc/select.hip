@@ -214,7 +214,7 @@ hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStre
 constexpr int kCoopBlock = 1024;
 constexpr int kCoopWaves = kCoopBlock / kWave;
 constexpr int kArgTile = kCoopBlock * 4;       // counters per argmax tile
-constexpr int kMaxInst = 1024;                  // instances per launch (LDS tables)
+constexpr int kMaxInst = kCoopBlock;             // instances per launch (LDS tables)
 
 template <typename T>
 __device__ __forceinline__ T ld_co(const T* p) {        // coherent load (all XCDs)
@@ -264,25 +264,37 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* bar, unsigned int& epoch)
     return s_ok != 0;
 }
 
+// Exclusive prefix of one int64 per thread of the block into out[0..blockDim], with
+// out[blockDim] the total.
+__device__ __forceinline__ void block_excl_scan_i64(int64_t v, int64_t* out, int64_t* wsum) {
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const int64_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        const int64_t t = lane < kCoopWaves ? wsum[lane] : 0;
+        const int64_t ti = wave_incl_scan(t);
+        if (lane < kCoopWaves) wsum[lane] = ti - t;
+        if (lane == kCoopWaves - 1) out[kCoopBlock] = ti;
+    }
+    __syncthreads();
+    out[tid] = incl - v + wsum[wid];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __restrict__ inst,
                                                             int32_t ninst, int32_t maxk,
                                                             GridBarrier* bar) {
     __shared__ int64_t tile_pre[kMaxInst + 1];    // argmax tiles per instance, prefix
     __shared__ int64_t ent_pre[kMaxInst + 1];     // cover entries per instance, prefix
     __shared__ int64_t ent_beg[kMaxInst];
-    __shared__ int32_t ent_u[kMaxInst];
     __shared__ unsigned long long red[kCoopWaves];
+    __shared__ int64_t wsum[kCoopWaves];
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     unsigned int epoch = 0;
-    if (tid == 0) {
-        int64_t acc = 0;
-        for (int i = 0; i < ninst; ++i) {
-            tile_pre[i] = acc;
-            acc += (inst[i].n + kArgTile - 1) / kArgTile;
-        }
-        tile_pre[ninst] = acc;
-    }
-    __syncthreads();
+    // instance prefixes are computed one instance per thread (kMaxInst == kCoopBlock); the
+    // tables past ninst repeat the total
+    block_excl_scan_i64(tid < ninst ? (inst[tid].n + kArgTile - 1) / kArgTile : 0, tile_pre, wsum);
     const int64_t ntiles = tile_pre[ninst];
     const int64_t gwave = (int64_t)blockIdx.x * kCoopWaves + wid;
     const int64_t nwaves = (int64_t)gridDim.x * kCoopWaves;
@@ -327,21 +339,16 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         }
         if (!grid_sync(bar, epoch)) return;
         // ---- cover: sets containing each instance's new seed ----
-        if (tid == 0) {
-            int64_t acc = 0;
-            for (int i = 0; i < ninst; ++i) {
-                ent_pre[i] = acc;
-                if (round < inst[i].k) {
-                    const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)ld_co(inst[i].keys + round));
-                    ent_u[i] = u;
-                    ent_beg[i] = inst[i].inv_off[u];
-                    acc += inst[i].inv_off[u + 1] - ent_beg[i];
-                    if (blockIdx.x == 0) st_co(inst[i].seeds + round, u);
-                }
-            }
-            ent_pre[ninst] = acc;
+        int64_t cnt = 0;
+        if (tid < ninst && round < inst[tid].k) {
+            const SelInst& I = inst[tid];
+            const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)ld_co(I.keys + round));
+            const int64_t beg = I.inv_off[u];
+            ent_beg[tid] = beg;
+            cnt = I.inv_off[u + 1] - beg;
+            if (blockIdx.x == 0) st_co(I.seeds + round, u);
         }
-        __syncthreads();
+        block_excl_scan_i64(cnt, ent_pre, wsum);
         const int64_t nent = ent_pre[ninst];
         unsigned long long mine = 0;
         int mine_inst = -1;
@@ -379,6 +386,8 @@ int select_coop_grid() {
         nb = 1;
     return cus * (nb < 2 ? nb : 2);
 }
+
+int select_max_inst() { return kMaxInst; }
 
 hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
                               hipStream_t s) {

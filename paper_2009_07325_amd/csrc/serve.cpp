@@ -127,9 +127,9 @@ void finish(imm_server* S, Query& q, imm_status st, const std::string& err) {
         info.theta = P.theta;
         info.num_rr = P.upto;
         info.covered = P.covered;
-        info.edges_examined = (int64_t)(sum64(p->host_ctr->edges) + sum64(p->host_ctr->hedges));
-        info.edges_heavy = (int64_t)sum64(p->host_ctr->hedges);
-        info.pool_ids = (int64_t)sum64(p->host_ctr->placed);
+        info.edges_examined = (int64_t)(p->sum.edges + p->sum.hedges);
+        info.edges_heavy = (int64_t)p->sum.hedges;
+        info.pool_ids = (int64_t)p->sum.placed;
         info.phases = P.phases;
         info.lb = P.lb;
         info.spread_est = P.spread_est();
@@ -199,7 +199,7 @@ bool tick(imm_server* S) {
         imm_status st = pool_generate(p, target, S->stream);
         const double dt = now_s() - t0;
         if (st == IMM_OK && p->count > 0)
-            S->mean_members[m].store((double)sum64(p->host_ctr->placed) / (double)p->count);
+            S->mean_members[m].store((double)p->sum.placed / (double)p->count);
         S->pool_sets[m].store(p->count);
         for (size_t i = 0; i < act.size();) {
             Query& q = act[i];
