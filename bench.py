@@ -169,7 +169,7 @@ def bench_batch(args) -> int:
     solo = []
     for j, it in enumerate(items):
         solo.append(solve(it))
-        if (j + 1) % 32 == 0:
+        if (j + 1) % 16 == 0:
             log(f"  sequential {j + 1}/{len(items)}: {time.perf_counter() - t0:.1f}s")
     t_seq = time.perf_counter() - t0
     service = [i["t_total_s"] for _, i in solo]
@@ -246,6 +246,26 @@ def bench_batch(args) -> int:
     return 0 if mismatched == 0 else 1
 
 
+def copy_calibration(nbytes: int, reps: int) -> int:
+    """Launches a plain device-to-device copy kernel of known size (torch's elementwise
+    copy of nbytes) `reps` times: the reference that scales HBM byte counters read under a
+    profiler (bytes read and written per dispatch are exactly nbytes each)."""
+    import torch
+    n = nbytes // 4
+    a = torch.arange(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ok = bool(torch.equal(a[-1024:], b[-1024:]))
+    print(json.dumps({"copy_bytes": n * 4, "reps": reps, "s_per_copy": dt,
+                      "gb_s": 2 * n * 4 / dt / 1e9, "ok": ok}), flush=True)
+    return 0 if ok else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +275,8 @@ def main() -> int:
     ap.add_argument("--instances", type=int, default=256, help="c4: instances of the mix")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy kernel of BYTES (profiler counter scale)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -263,6 +285,8 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration, 5)
     if args.workload == "c4":
         log("host:", json.dumps(host_info()))
         return bench_batch(args)

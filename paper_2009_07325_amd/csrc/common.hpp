@@ -20,6 +20,27 @@ struct alignas(16) VRec {
     uint32_t deg;
     uint32_t thr;
 };
+// Pointers read from device memory (per-instance descriptors) are generic to the
+// compiler, which then emits flat accesses; global() restates that they address HBM so
+// that loads, stores and atomics through them are global_* instructions.
+#define IMM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ IMM_GLOBAL T* global(T* p) {
+    return (IMM_GLOBAL T*)p;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One 16-byte load of a vertex record.
+__device__ __forceinline__ VRec load_vrec(const IMM_GLOBAL VRec* p) {
+    const u32x4 v = *reinterpret_cast<const IMM_GLOBAL u32x4*>(p);
+    VRec r;
+    r.start = (int64_t)(((uint64_t)v.y << 32) | v.x);
+    r.deg = v.z;
+    r.thr = v.w;
+    return r;
+}
+
 constexpr uint32_t kUniformBit = 0x80000000u;
 constexpr uint32_t kDegMask = 0x7FFFFFFFu;
 
@@ -111,6 +132,11 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 
 template <typename T>
 __device__ __forceinline__ T atomic_add_agent(T* p, T v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T atomic_add_agent(IMM_GLOBAL T* p, T v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -78,7 +78,7 @@ __device__ __forceinline__ int32_t find_inst(const GenLaunch& L, int64_t w) {
 
 __device__ __forceinline__ void flush_counters(const GenLaunch& L, WaveState& ws, int64_t slot) {
     if (ws.place_inst >= 0 && lane_id() == 0) {
-        PoolCounters* c = L.inst[ws.place_inst].ctr;
+        IMM_GLOBAL PoolCounters* c = global(L.inst[ws.place_inst].ctr);
         if (ws.placed) atomic_add_agent(&c->placed[slot & 63], ws.placed);
         if (ws.edges)
             atomic_add_agent(L.heavy_in ? &c->hedges[slot & 63] : &c->edges[slot & 63], ws.edges);
@@ -115,7 +115,7 @@ __device__ __forceinline__ bool next_set(const GenLaunch& L, WaveState& ws, int3
     inst = ws.inst;
     const GenInst& I = L.inst[inst];
     const int64_t j = w - ws.inst_lo;
-    r = uniform(I.list ? I.list[j] : (uint32_t)(I.first + j));
+    r = uniform(I.list ? global(I.list)[j] : (uint32_t)(I.first + j));
     return true;
 }
 
@@ -134,8 +134,8 @@ __device__ __forceinline__ void push_heavy(const GenLaunch& L, WaveState& ws, in
 }
 
 __device__ __forceinline__ void push_capacity_miss(const GenInst& I, uint32_t r) {
-    const unsigned int at = atomic_add_agent(&I.ctr->n_capacity, 1u);
-    I.cap_list[at] = r;
+    const unsigned int at = atomic_add_agent(&global(I.ctr)->n_capacity, 1u);
+    global(I.cap_list)[at] = r;
 }
 
 // Write a finished set (members list[0..size)) into its pool; wave-cooperative.
@@ -151,7 +151,7 @@ __device__ void place_wave(const GenLaunch& L, WaveState& ws, int64_t slot, int3
     if (ws.chunk_left < size) {
         const int32_t want = max(kIdChunk, size);
         unsigned long long base = 0;
-        if (lane == 0) base = atomic_add_agent(&I.ctr->tail, (unsigned long long)want);
+        if (lane == 0) base = atomic_add_agent(&global(I.ctr)->tail, (unsigned long long)want);
         base = uniform64(base);
         if ((int64_t)base + want > I.cap_ids) {
             if (lane == 0) push_capacity_miss(I, r);
@@ -161,14 +161,16 @@ __device__ void place_wave(const GenLaunch& L, WaveState& ws, int64_t slot, int3
         ws.chunk_base = base;
         ws.chunk_left = want;
     }
+    IMM_GLOBAL int32_t* ids = global(I.ids);
+    IMM_GLOBAL uint32_t* hist = global(I.hist);
     for (int32_t i = lane; i < size; i += kWave) {
         const int32_t v = list[i];
-        I.ids[ws.chunk_base + i] = v;
-        __hip_atomic_fetch_add(I.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ids[ws.chunk_base + i] = v;
+        __hip_atomic_fetch_add(hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
-        I.rr_start[r] = (int64_t)ws.chunk_base;
-        I.rr_len[r] = size;
+        global(I.rr_start)[r] = (int64_t)ws.chunk_base;
+        global(I.rr_len)[r] = size;
     }
     ws.chunk_base += (unsigned long long)size;
     ws.chunk_left -= size;
@@ -191,79 +193,122 @@ constexpr int32_t kBigGroups = 48;
 
 // The graph fields a set's traversal reads, loaded once per set into registers.
 struct GraphView {
-    const VRec* vrec;
-    const int32_t* src;
-    const uint32_t* w;       // IC thresholds or LT cumulative thresholds
+    const IMM_GLOBAL VRec* vrec;
+    const IMM_GLOBAL int32_t* src;
+    const IMM_GLOBAL uint32_t* w;       // IC thresholds or LT cumulative thresholds
     uint32_t k0, k1;
     int32_t n;
 };
 
 __device__ __forceinline__ GraphView ic_view(const GenInst& I) {
-    return GraphView{I.vrec, I.src, I.thr, I.k0, I.k1, I.n};
+    return GraphView{global(I.vrec), global(I.src), global(I.thr), I.k0, I.k1, I.n};
 }
 
 __device__ __forceinline__ GraphView lt_view(const GenInst& I) {
-    return GraphView{I.vrec, I.src, I.cum, I.k0, I.k1, I.n};
+    return GraphView{global(I.vrec), global(I.src), global(I.cum), I.k0, I.k1, I.n};
 }
 
-// Tests the in-edges of group g that lie in [s, e_end) for set r.  Live edges whose source
-// is newly visited are returned in w[] with fresh[] set.
-__device__ __forceinline__ void test_group(const GraphView& a, uint32_t r, uint32_t g, uint32_t s,
-                                           uint32_t e_end, bool uniform_thr, uint32_t uthr,
-                                           uint32_t* vis, int32_t w[4], bool fresh[4]) {
+// Draws the in-edges of group g (edges 4g .. 4g+3) for set r; bit j of the result is set
+// when edge 4g + j lies in [s, e_end) and is live.  Pure ALU apart from the per-edge
+// thresholds of a non-uniform vertex.
+__device__ __forceinline__ uint32_t live_bits(const GraphView& a, uint32_t r, uint32_t g,
+                                              uint32_t s, uint32_t e_end, bool uniform_thr,
+                                              uint32_t uthr) {
     const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, a.k0, a.k1);
-    uint32_t t[4];
-    if (uniform_thr) {
-        t[0] = t[1] = t[2] = t[3] = uthr;
-    } else {
-        const uint4 tv = *reinterpret_cast<const uint4*>(a.w + ((int64_t)g << 2));
-        t[0] = tv.x; t[1] = tv.y; t[2] = tv.z; t[3] = tv.w;
-    }
     const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+    // edge 4g + j is in the vertex's list iff its offset 4g + j - s (mod 2^32) is below d
+    const uint32_t d = e_end - s, o = (g << 2) - s;
+    uint32_t bits = 0;
+    if (uniform_thr) {
+        const bool always = uthr == kAlways;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bits |= (uint32_t)(o + j < d && (always || xs[j] < uthr)) << j;
+    } else {
+        const u32x4 tv = *reinterpret_cast<const IMM_GLOBAL u32x4*>(a.w + ((int64_t)g << 2));
+        const uint32_t t[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bits |= (uint32_t)(o + j < d && (t[j] == kAlways || xs[j] < t[j])) << j;
+    }
+    return bits;
+}
+
+// Live edges are staged in LDS (edge indices, per wave) and resolved in batches: the
+// source loads and visited test-and-sets of a whole batch are issued together, so the
+// group tests themselves never wait on memory.
+constexpr int kStage = 128;
+
+// Appends the live edges of one pass (bits of group g per lane) to the wave's stage,
+// calling flush() first whenever they would not fit.
+template <class Flush>
+__device__ __forceinline__ void stage_edges(uint32_t* stage, int32_t& n, uint32_t bits,
+                                            uint32_t g, Flush&& flush) {
+    if (ballot(bits != 0u) == 0) return;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const uint32_t e = (g << 2) + j;
-        const bool live = e >= s && e < e_end && (t[j] == kAlways || xs[j] < t[j]);
-        if (live) {
-            w[j] = a.src[e];
-            fresh[j] = vis_test_and_set(vis, w[j]);
-        }
+        const bool l = (bits >> j) & 1u;
+        const uint64_t m = ballot(l);
+        if (m == 0) continue;
+        const int32_t c = (int32_t)__popcll(m);
+        if (n + c > kStage) flush();
+        if (l) stage[n + (int32_t)lanes_below(m)] = (g << 2) + j;
+        n += c;
     }
 }
 
-// Wave-level append into an on-chip list of capacity `cap`; on overflow the set is
-// abandoned (and the bits of the vertices not appended are cleared).
-__device__ __forceinline__ void append_wave(int32_t* list, int32_t& size, int32_t cap,
-                                            bool& abandon, uint32_t* vis, const int32_t w[4],
-                                            const bool fresh[4]) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint64_t mask = ballot(fresh[j]);
-        const int32_t cnt = (int32_t)__popcll(mask);
-        if (cnt == 0) continue;
-        if (abandon || size + cnt > cap) {
+// Resolves up to 64 staged edges: source of edge stage[i] for i = i0 + lane < n, and
+// whether this test-and-set visited it first.
+__device__ __forceinline__ bool resolve_staged(const GraphView& a, const uint32_t* stage,
+                                               int32_t i0, int32_t n, uint32_t* vis,
+                                               int32_t& u) {
+    const int32_t i = i0 + lane_id();
+    if (i >= n) return false;
+    u = a.src[stage[i]];
+    return vis_test_and_set(vis, u);
+}
+
+// Light kernel: appends the new sources of the staged edges to the on-chip list; on
+// overflow the set is abandoned (and the bits of the vertices not appended are cleared).
+__device__ __forceinline__ void flush_light(const GraphView& a, uint32_t* stage, int32_t& n,
+                                            int32_t* list, int32_t& size, bool& abandon,
+                                            uint32_t* vis) {
+    wave_sync();
+    for (int32_t i0 = 0; i0 < n; i0 += kWave) {
+        int32_t u = 0;
+        const bool fresh = resolve_staged(a, stage, i0, n, vis, u);
+        const uint64_t m = ballot(fresh);
+        const int32_t c = (int32_t)__popcll(m);
+        if (c == 0) continue;
+        if (abandon || size + c > kLightCap) {
             abandon = true;
-            if (fresh[j]) vis_clear(vis, w[j]);
+            if (fresh) vis_clear(vis, u);
             continue;
         }
-        if (fresh[j]) list[size + (int32_t)lanes_below(mask)] = w[j];
-        size += cnt;
+        if (fresh) list[size + (int32_t)lanes_below(m)] = u;
+        size += c;
     }
+    n = 0;
+    wave_sync();
 }
 
-// Workgroup-level append into an HBM list (positions from an LDS counter).
-__device__ __forceinline__ void append_block(int32_t* list, int32_t* s_size, const int32_t w[4],
-                                             const bool fresh[4]) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint64_t mask = ballot(fresh[j]);
-        const int32_t cnt = (int32_t)__popcll(mask);
-        if (cnt == 0) continue;
+// Heavy kernel: appends to the workgroup's HBM list (positions from an LDS counter).
+__device__ __forceinline__ void flush_block(const GraphView& a, uint32_t* stage, int32_t& n,
+                                            int32_t* list, int32_t* s_size, uint32_t* vis) {
+    wave_sync();
+    for (int32_t i0 = 0; i0 < n; i0 += kWave) {
+        int32_t u = 0;
+        const bool fresh = resolve_staged(a, stage, i0, n, vis, u);
+        const uint64_t m = ballot(fresh);
+        const int32_t c = (int32_t)__popcll(m);
+        if (c == 0) continue;
         int32_t at = 0;
-        if (lane_id() == 0) at = atomicAdd(s_size, cnt);
+        if (lane_id() == 0) at = atomicAdd(s_size, c);
         at = __shfl(at, 0, kWave);
-        if (fresh[j]) list[at + (int32_t)lanes_below(mask)] = w[j];
+        if (fresh) list[at + (int32_t)lanes_below(m)] = u;
     }
+    n = 0;
+    wave_sync();
 }
 
 __device__ __forceinline__ uint32_t groups_of(uint32_t start, uint32_t deg) {
@@ -282,6 +327,7 @@ struct FrontierLds {
 
 struct LightLds {
     FrontierLds f;
+    uint32_t stage[kStage];
     int32_t list[kLightCap];
 };
 
@@ -314,7 +360,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             const int32_t nb = min(size - head, kWave);
             uint32_t ng = 0, dg = 0, st = 0, dgf = 0, th = 0;
             if (lane < nb) {
-                const VRec rec = a.vrec[list[head + lane]];
+                const VRec rec = load_vrec(a.vrec + list[head + lane]);
                 dgf = rec.deg;
                 th = rec.thr;
                 dg = dgf & kDegMask;
@@ -341,6 +387,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             }
             used += total;
 
+            int32_t nst = 0;
+            auto flush = [&]() { flush_light(a, L.stage, nst, list, size, abandon, vis); };
             // big vertices: one at a time, wave-uniform vertex data
             uint64_t bigmask = ballot(big);
             while (bigmask && !abandon) {
@@ -352,22 +400,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
                 const uint32_t gb = __builtin_amdgcn_readlane(ng, b);
                 const uint32_t e_end = s0 + (df & kDegMask);
                 const uint32_t g0 = s0 >> 2;
+                const bool uni = (df & kUniformBit) != 0;
                 for (uint32_t base = 0; base < gb && !abandon; base += kWave) {
-                    int32_t w[4] = {0, 0, 0, 0};
-                    bool fresh[4] = {false, false, false, false};
-                    if (base + lane < gb)
-                        test_group(a, r, g0 + base + lane, s0, e_end, (df & kUniformBit) != 0, t0,
-                                   vis, w, fresh);
-                    append_wave(list, size, kLightCap, abandon, vis, w, fresh);
+                    const uint32_t g = g0 + base + lane;
+                    const uint32_t bits =
+                        base + lane < gb ? live_bits(a, r, g, s0, e_end, uni, t0) : 0u;
+                    stage_edges(L.stage, nst, bits, g, flush);
                 }
             }
-            wave_sync();
 
             // small vertices: packed, each lane searches for its vertex
             for (int32_t base = 0; base < total_small && !abandon; base += kWave) {
                 const int32_t q = base + lane;
-                int32_t w[4] = {0, 0, 0, 0};
-                bool fresh[4] = {false, false, false, false};
+                uint32_t bits = 0, g = 0;
                 if (q < total_small) {
                     int32_t lo = 0, hi = nb;   // pre[lo] <= q < pre[hi]
                     while (hi - lo > 1) {
@@ -376,11 +421,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
                     }
                     const uint32_t s0 = L.f.start[lo];
                     const uint32_t dd = L.f.deg[lo];
-                    test_group(a, r, (s0 >> 2) + (uint32_t)(q - L.f.pre[lo]), s0, s0 + (dd & kDegMask),
-                               (dd & kUniformBit) != 0, L.f.thr[lo], vis, w, fresh);
+                    g = (s0 >> 2) + (uint32_t)(q - L.f.pre[lo]);
+                    bits = live_bits(a, r, g, s0, s0 + (dd & kDegMask), (dd & kUniformBit) != 0,
+                                     L.f.thr[lo]);
                 }
-                append_wave(list, size, kLightCap, abandon, vis, w, fresh);
+                stage_edges(L.stage, nst, bits, g, flush);
             }
+            if (nst > 0) flush();
             wave_sync();
             head += nb;
         }
@@ -396,17 +443,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 // ------------------------------------------------------------------------------------
 // IC heavy kernel: one workgroup per set, member list in HBM.
 // ------------------------------------------------------------------------------------
-// Inclusive block scan of one int per thread (up to 1024 threads).
+// Inclusive block scan of one uint64 per thread (up to 1024 threads).
 template <int kHeavyBlock>
-__device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* wsum) {
+__device__ __forceinline__ uint64_t block_incl_scan(uint64_t v, uint64_t* wsum) {
     constexpr int kHeavyWaves = kHeavyBlock / kWave;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    int32_t incl = wave_incl_scan(v);
+    uint64_t incl = wave_incl_scan(v);
     if (lane == kWave - 1) wsum[wid] = incl;
     __syncthreads();
     if (wid == 0) {
-        int32_t t = lane < kHeavyWaves ? wsum[lane] : 0;
-        int32_t ti = wave_incl_scan(t);
+        const uint64_t t = lane < kHeavyWaves ? wsum[lane] : 0;
+        const uint64_t ti = wave_incl_scan(t);
         if (lane < kHeavyWaves) wsum[lane] = ti - t;
     }
     __syncthreads();
@@ -415,22 +462,32 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* wsum) {
     return incl;
 }
 
+// Each batch of up to kHeavyBlock frontier vertices is split into work for independent
+// waves: vertices with at least kWave groups ("big") are cut into chunks of kWave groups,
+// chunk c going to wave c mod (waves per block); the other vertices are packed into
+// windows of kWave groups, handed out the same way.  One block scan per batch yields, per
+// vertex, its small-group prefix, its index among the big vertices and its first chunk,
+// packed in one 64-bit value (fields of 16, 16 and 32 bits: a batch has at most 1024
+// vertices, each with fewer than kWave groups in the first field).
 template <int kHeavyBlock>
 __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenLaunch G) {
     constexpr int kHeavyWaves = kHeavyBlock / kWave;
-    constexpr uint32_t kBigHeavy = kHeavyBlock / 4;
     __shared__ int32_t pre[kHeavyBlock + 1];
     __shared__ uint32_t st[kHeavyBlock], dgs[kHeavyBlock], ths[kHeavyBlock];
     __shared__ uint32_t bst[kHeavyBlock], bdg[kHeavyBlock], bth[kHeavyBlock], bng[kHeavyBlock];
-    __shared__ int32_t wsum[kHeavyWaves];
+    __shared__ uint32_t bcp[kHeavyBlock + 1];
+    __shared__ uint32_t stage_all[kHeavyWaves][kStage];
+    __shared__ uint64_t wsum[kHeavyWaves];
     __shared__ unsigned long long wred[kHeavyWaves];
-    __shared__ int32_t s_size, s_nbig;
+    __shared__ int32_t s_size;
+    __shared__ uint32_t s_nchunks;
     __shared__ unsigned int s_idx;
     __shared__ unsigned long long s_base;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int64_t slot = blockIdx.x;
     uint32_t* vis = G.hvisited + slot * G.vis_words;
     int32_t* list = G.hlist + slot * G.list_stride;
+    uint32_t* stage = stage_all[wid];
 
     for (;;) {
         if (tid == 0) s_idx = atomic_add_agent(&G.lc->hwork, 1u);
@@ -452,71 +509,92 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenLaunch G) {
         unsigned long long examined = 0;
         while (head < size) {
             const int32_t nb = min(size - head, kHeavyBlock);
-            if (tid == 0) s_nbig = 0;
             uint32_t ng = 0, dg = 0, s0 = 0, dgf = 0, t0 = 0;
             if (tid < nb) {
-                const VRec rec = a.vrec[list[head + tid]];
+                const VRec rec = load_vrec(a.vrec + list[head + tid]);
                 dgf = rec.deg;
                 t0 = rec.thr;
                 dg = dgf & kDegMask;
                 s0 = (uint32_t)rec.start;
                 ng = groups_of(s0, dg);
             }
-            const bool big = ng >= kBigHeavy;
-            const int32_t ngs = big ? 0 : (int32_t)ng;
+            const bool big = ng >= (uint32_t)kWave;
+            const uint64_t mine =
+                big ? ((uint64_t)((ng + kWave - 1) / kWave) << 32) | (1ull << 16) : (uint64_t)ng;
             const unsigned long long dsum = wave_sum((unsigned long long)dg);
             if (lane == 0) wred[wid] = dsum;
-            const int32_t incl = block_incl_scan<kHeavyBlock>(ngs, wsum);   // has barriers
+            const uint64_t incl = block_incl_scan<kHeavyBlock>(mine, wsum);   // has barriers
+            const uint64_t excl = incl - mine;
             if (tid < nb) {
-                pre[tid] = incl - ngs;
+                pre[tid] = (int32_t)(excl & 0xFFFFu);
                 st[tid] = s0;
                 dgs[tid] = dgf;
                 ths[tid] = t0;
                 if (big) {
-                    const int32_t k = atomicAdd(&s_nbig, 1);
+                    const uint32_t k = (uint32_t)(excl >> 16) & 0xFFFFu;
                     bst[k] = s0;
                     bdg[k] = dgf;
                     bth[k] = t0;
                     bng[k] = ng;
+                    bcp[k] = (uint32_t)(excl >> 32);
                 }
             }
-            if (tid == nb - 1) pre[nb] = incl;
+            if (tid == kHeavyBlock - 1) {          // block totals
+                const uint32_t nbig = (uint32_t)(incl >> 16) & 0xFFFFu;
+                pre[nb] = (int32_t)(incl & 0xFFFFu);
+                bcp[nbig] = (uint32_t)(incl >> 32);
+                s_nchunks = (uint32_t)(incl >> 32);
+            }
             __syncthreads();
             if (tid == 0)
                 for (int w = 0; w < kHeavyWaves; ++w) examined += wred[w];
-            const int32_t nbig = s_nbig;
-            // big vertices: all threads on consecutive groups of one vertex
-            for (int32_t i = 0; i < nbig; ++i) {
-                const uint32_t bs = bst[i], bd = bdg[i], bt = bth[i], gb = bng[i];
-                const uint32_t e_end = bs + (bd & kDegMask), g0 = bs >> 2;
-                for (uint32_t base = 0; base < gb; base += kHeavyBlock) {
-                    int32_t w[4] = {0, 0, 0, 0};
-                    bool fresh[4] = {false, false, false, false};
-                    if (base + tid < gb)
-                        test_group(a, r, g0 + base + tid, bs, e_end, (bd & kUniformBit) != 0, bt, vis,
-                                   w, fresh);
-                    append_block(list, &s_size, w, fresh);
+            const uint32_t nchunks = uniform(s_nchunks);
+            const int32_t total_small = uniform(pre[nb]);
+            int32_t nst = 0;
+            auto flush = [&]() { flush_block(a, stage, nst, list, &s_size, vis); };
+            // big vertices: chunk c -> the vertex k with bcp[k] <= c < bcp[k + 1]; a wave's
+            // chunks increase, so its vertex index only moves forward
+            uint32_t k = ~0u, c_lo = 0, c_hi = 0;   // chunks [c_lo, c_hi) are vertex k's
+            uint32_t bs = 0, be = 0, bt = 0, gb = 0;
+            bool bu = false;
+            for (uint32_t c = (uint32_t)wid; c < nchunks; c += kHeavyWaves) {
+                if (c >= c_hi) {
+                    do {
+                        ++k;
+                        c_hi = uniform(bcp[k + 1]);
+                    } while (c_hi <= c);
+                    c_lo = uniform(bcp[k]);
+                    bs = uniform(bst[k]);
+                    const uint32_t bd = uniform(bdg[k]);
+                    be = bs + (bd & kDegMask);
+                    bu = (bd & kUniformBit) != 0;
+                    bt = uniform(bth[k]);
+                    gb = uniform(bng[k]);
                 }
+                const uint32_t q = (c - c_lo) * kWave + lane;
+                const uint32_t g = (bs >> 2) + q;
+                const uint32_t bits = q < gb ? live_bits(a, r, g, bs, be, bu, bt) : 0u;
+                stage_edges(stage, nst, bits, g, flush);
             }
-            // small vertices, packed
-            const int32_t total = pre[nb];
-            for (int32_t base = 0; base < total; base += kHeavyBlock) {
-                const int32_t q = base + tid;
-                int32_t w[4] = {0, 0, 0, 0};
-                bool fresh[4] = {false, false, false, false};
-                if (q < total) {
-                    int32_t lo = 0, hi = nb;
+            // small vertices: windows of kWave groups, each lane searches for its vertex
+            for (int32_t base = wid * kWave; base < total_small; base += kHeavyBlock) {
+                const int32_t q = base + lane;
+                uint32_t bits = 0, g = 0;
+                if (q < total_small) {
+                    int32_t lo = 0, hi = nb;   // pre[lo] <= q < pre[hi]
                     while (hi - lo > 1) {
                         const int32_t mid = (lo + hi) >> 1;
                         if (pre[mid] <= q) lo = mid; else hi = mid;
                     }
                     const uint32_t ss = st[lo];
                     const uint32_t dd = dgs[lo];
-                    test_group(a, r, (ss >> 2) + (uint32_t)(q - pre[lo]), ss, ss + (dd & kDegMask),
-                               (dd & kUniformBit) != 0, ths[lo], vis, w, fresh);
+                    g = (ss >> 2) + (uint32_t)(q - pre[lo]);
+                    bits = live_bits(a, r, g, ss, ss + (dd & kDegMask), (dd & kUniformBit) != 0,
+                                     ths[lo]);
                 }
-                append_block(list, &s_size, w, fresh);
+                stage_edges(stage, nst, bits, g, flush);
             }
+            if (nst > 0) flush();
             __syncthreads();
             head += nb;
             size = s_size;
@@ -524,25 +602,28 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenLaunch G) {
         }
         // place the set
         if (tid == 0) {
-            unsigned long long b = atomic_add_agent(&I.ctr->tail, (unsigned long long)size);
+            IMM_GLOBAL PoolCounters* c = global(I.ctr);
+            unsigned long long b = atomic_add_agent(&c->tail, (unsigned long long)size);
             if ((int64_t)b + size > I.cap_ids) {
                 push_capacity_miss(I, r);
                 b = ~0ull;
             } else {
-                I.rr_start[r] = (int64_t)b;
-                I.rr_len[r] = size;
-                atomic_add_agent(&I.ctr->placed[slot & 63], (unsigned long long)size);
-                atomic_add_agent(&I.ctr->hedges[slot & 63], (unsigned long long)examined);
+                global(I.rr_start)[r] = (int64_t)b;
+                global(I.rr_len)[r] = size;
+                atomic_add_agent(&c->placed[slot & 63], (unsigned long long)size);
+                atomic_add_agent(&c->hedges[slot & 63], (unsigned long long)examined);
             }
             s_base = b;
         }
         __syncthreads();
         const unsigned long long b = s_base;
+        IMM_GLOBAL int32_t* ids = global(I.ids);
+        IMM_GLOBAL uint32_t* hist = global(I.hist);
         for (int32_t i = tid; i < size; i += kHeavyBlock) {
             const int32_t v = list[i];
             if (b != ~0ull) {
-                I.ids[b + i] = v;
-                __hip_atomic_fetch_add(I.hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ids[b + i] = v;
+                __hip_atomic_fetch_add(hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             vis_clear(vis, v);
         }
@@ -614,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
         uint64_t examined = 0;
         bool abandon = false;
         for (;;) {
-            const VRec rec = a.vrec[v];
+            const VRec rec = load_vrec(a.vrec + v);
             const uint32_t d = rec.deg & kDegMask;
             if (d == 0) break;
             examined += d;

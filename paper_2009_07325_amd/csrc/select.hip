@@ -11,6 +11,9 @@
 //                  index so that a round touches only the sets that contain u.
 // Integer decrements commute, so counters, seeds and the covered count are the same for
 // any schedule.
+#include <cstdlib>
+#include <cstring>
+
 #include "kernels.hpp"
 
 namespace imm {
@@ -389,9 +392,25 @@ int select_coop_grid() {
 
 int select_max_inst() { return kMaxInst; }
 
+// IMM_SELECT_LAUNCH=plain launches the same grid with an ordinary launch.  The grid is
+// sized to be co-resident on an idle device, so the result is the same; the switch exists
+// for tools that do not handle cooperative launches (some profilers).  If blocks were ever
+// not co-resident, the barrier's bounded wait reports an error instead of hanging.
+static bool plain_launch() {
+    static const bool plain = [] {
+        const char* e = getenv("IMM_SELECT_LAUNCH");
+        return e && strcmp(e, "plain") == 0;
+    }();
+    return plain;
+}
+
 hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
                               hipStream_t s) {
     if (ninst < 1 || ninst > kMaxInst) return hipErrorInvalidValue;
+    if (plain_launch()) {
+        k_select_coop<<<select_coop_grid(), kCoopBlock, 0, s>>>(inst, ninst, maxk, bar);
+        return hipGetLastError();
+    }
     void* args[] = {(void*)&inst, (void*)&ninst, (void*)&maxk, (void*)&bar};
     return hipLaunchCooperativeKernel((const void*)k_select_coop, dim3(select_coop_grid()),
                                       dim3(kCoopBlock), args, 0, s);
