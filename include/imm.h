@@ -97,6 +97,11 @@ imm_status imm_init(int32_t device);
 /* Thread-local message for the last non-OK status ("" if none). */
 const char* imm_last_error(void);
 
+/* Device memory that objects release is kept by the library for reuse (at most 64 GiB per
+ * device; it is also given back automatically when an allocation fails).  This returns all
+ * of it to the HIP runtime.  Thread-safe. */
+imm_status imm_release_cached_memory(void);
+
 /* Upload a directed graph G = (V, E), gIM Sec. II-A, as the CSR of its transpose
  * (in-edges), and encode edge probabilities into 32-bit thresholds on the device.
  *   n        vertices, n >= 2

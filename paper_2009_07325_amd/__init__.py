@@ -24,7 +24,8 @@ STATUS = {0: "IMM_OK", 1: "IMM_EINVAL", 2: "IMM_ENOMEM", 3: "IMM_ECAPACITY", 4: 
           5: "IMM_ENOTIMPL", 6: "IMM_EBUSY", 7: "IMM_ECANCELLED"}
 
 # every entry point declared in include/imm.h
-EXPORTS = ("imm_init", "imm_last_error", "imm_graph_create", "imm_graph_destroy",
+EXPORTS = ("imm_init", "imm_last_error", "imm_release_cached_memory", "imm_graph_create",
+           "imm_graph_destroy",
            "imm_graph_info", "imm_graph_export_encoding", "imm_pool_create", "imm_pool_destroy",
            "imm_pool_size", "imm_generate_rr", "imm_rr_export", "imm_rr_histogram",
            "imm_select_seeds", "imm_solve", "imm_solve_pool", "imm_log_binom",
@@ -108,6 +109,7 @@ def lib() -> ctypes.CDLL:
         pp = ctypes.POINTER(ctypes.c_void_p)
         sig = {
             "imm_init": [i32],
+            "imm_release_cached_memory": [],
             "imm_graph_create": [i32, i64, p, p, p, p, u32, pp],
             "imm_graph_destroy": [p],
             "imm_graph_info": [p, p, p, p, p],
@@ -247,6 +249,10 @@ def imm_rr_histogram(p, first: int, count: int, n: int) -> np.ndarray:
     h = np.zeros(n, dtype=np.uint32)
     _check(lib().imm_rr_histogram(p, first, count, _ptr(h)))
     return h
+
+
+def imm_release_cached_memory() -> None:
+    _check(lib().imm_release_cached_memory())
 
 
 def imm_select_seeds(p, first: int, count: int, k: int, stream=None) -> tuple[np.ndarray, int]:

@@ -32,7 +32,12 @@ imm_status GenCtx::init(int device_, imm_model model_, int cus_) {
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventCreate(&ev2));
     if (const char* b = getenv("IMM_LIGHT_BUDGET")) budget = std::max(1ll, atoll(b));
-    if (const char* b = getenv("IMM_HEAVY_BLOCK")) heavy_block = atoi(b) == 1024 ? 1024 : 256;
+    if (const char* b = getenv("IMM_HEAVY_SCRATCH_GIB"))
+        heavy_scratch = std::max(1ll, atoll(b)) << 30;
+    if (const char* b = getenv("IMM_HEAVY_BLOCK")) {
+        const int v = atoi(b);
+        if (v == 64 || v == 128 || v == 256 || v == 1024) heavy_block = v;
+    }
     return IMM_OK;
 }
 
@@ -84,14 +89,18 @@ imm_status ensure_light(GenCtx* c, int64_t n) {
 }
 
 // Heavy scratch: slots (IC one per workgroup, LT one per wave) each with a bitmap and a
-// member list of vis_n entries, bounded to ~4 GiB.
+// member list of vis_n entries, bounded to c->heavy_scratch bytes (fewer concurrent heavy
+// sets on huge graphs).
 imm_status ensure_heavy(GenCtx* c) {
     if (c->hlist) return IMM_OK;
     const bool lt = c->model == IMM_LT;
     const int64_t n = c->vis_n;
     int64_t want = lt ? (int64_t)c->cus * gen_blocks_per_cu(3) * 4
-                      : (int64_t)c->cus * gen_blocks_per_cu(c->heavy_block == 1024 ? 1 : 4);
-    int64_t cap = std::max<int64_t>(4, ((int64_t)4 << 30) / (4 * n + 4 * c->vis_words));
+                      : (int64_t)c->cus * gen_blocks_per_cu(c->heavy_block == 1024 ? 1
+                                                            : c->heavy_block == 256  ? 4
+                                                            : c->heavy_block == 128  ? 5
+                                                                                     : 6);
+    int64_t cap = std::max<int64_t>(4, c->heavy_scratch / (4 * n + 4 * c->vis_words));
     int64_t slots = std::min(want, cap);
     if (lt) slots = std::max<int64_t>(4, (slots / 4) * 4);
     IMM_TRY(dalloc(&c->hlist, slots * n));

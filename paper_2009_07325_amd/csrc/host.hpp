@@ -32,23 +32,28 @@ imm_status fail(imm_status st, const char* fmt, ...);
 
 constexpr int64_t kMaxSets = (int64_t)INT32_MAX;   // RR index and counters fit int32
 
+// Device memory goes through a caching allocator (devmem.cpp): blocks freed after their
+// work completed are reused by later requests of similar size.
+hipError_t dev_alloc(void** out, size_t bytes);
+void dev_free(void* p);
+size_t dev_cached_bytes();
+
 template <typename T>
 imm_status dalloc(T** p, int64_t count) {
     *p = nullptr;
     if (count <= 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(IMM_ENOMEM, "hipMalloc of %lld bytes failed: %s",
+    void* q = nullptr;
+    hipError_t e = dev_alloc(&q, sizeof(T) * (size_t)count);
+    if (e != hipSuccess)
+        return fail(IMM_ENOMEM, "device allocation of %lld bytes failed: %s",
                     (long long)(sizeof(T) * count), hipGetErrorString(e));
-    }
+    *p = static_cast<T*>(q);
     return IMM_OK;
 }
 
 template <typename T>
 void dfree(T*& p) {
-    if (p) (void)hipFree(p);
+    dev_free((void*)p);
     p = nullptr;
 }
 
@@ -71,11 +76,11 @@ imm_status dgrow(T** p, int64_t* cap, int64_t need, int64_t keep, hipStream_t s)
         hipError_t e = hipMemcpyAsync(q, *p, sizeof(T) * (size_t)keep, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
-            (void)hipFree(q);
+            dfree(q);
             return fail(IMM_EDEVICE, "grow copy failed: %s", hipGetErrorString(e));
         }
     }
-    if (*p) (void)hipFree(*p);
+    dfree(*p);
     *p = q;
     *cap = nc;
     return IMM_OK;
@@ -193,7 +198,8 @@ struct GenCtx {
     uint32_t* hvisited = nullptr;
     int32_t* hlist = nullptr;           // hslots lists of vis_n entries
     int64_t budget = 4096;              // light-wave group budget per set
-    int heavy_block = 256;              // threads per heavy set (256 or 1024)
+    int heavy_block = 256;              // threads per heavy set (64, 128, 256 or 1024)
+    int64_t heavy_scratch = (int64_t)16 << 30;   // bytes of heavy bitmaps + lists at most
 
     LaunchCounters* lc = nullptr;
     LaunchCounters* host_lc = nullptr;  // pinned

@@ -95,14 +95,15 @@ struct GenLaunch {
 };
 
 hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s);   // 256-thread blocks
-hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s);  // 256 or 1024
+// block: threads per heavy set, 64, 128, 256 or 1024
+hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s);
 hipError_t launch_lt(const GenLaunch& a, bool big, int grid, hipStream_t s);
 int rr_light_capacity();
 // Sums each instance's spread counters into out[i] and clears its n_capacity.
 hipError_t launch_pool_summary(const GenInst* inst, int32_t ninst, PoolSummary* out,
                                hipStream_t s);
 // occupancy in blocks per CU: 0 IC light, 1 IC heavy (1024), 2 LT, 3 LT with HBM lists,
-// 4 IC heavy (256)
+// 4 IC heavy (256), 5 IC heavy (128), 6 IC heavy (64)
 int gen_blocks_per_cu(int which);
 
 // Sorts each set's members ascending into the host-bound export buffer.

@@ -735,8 +735,13 @@ hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s) {
 }
 
 hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s) {
-    if (block == 256) k_ic_heavy<256><<<grid, 256, 0, s>>>(a);
-    else k_ic_heavy<1024><<<grid, 1024, 0, s>>>(a);
+    switch (block) {
+        case 64: k_ic_heavy<64><<<grid, 64, 0, s>>>(a); break;
+        case 128: k_ic_heavy<128><<<grid, 128, 0, s>>>(a); break;
+        case 256: k_ic_heavy<256><<<grid, 256, 0, s>>>(a); break;
+        case 1024: k_ic_heavy<1024><<<grid, 1024, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -753,6 +758,8 @@ int gen_blocks_per_cu(int which) {
         case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_light, kBlock, 0); break;
         case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<1024>, 1024, 0); break;
         case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<256>, 256, 0); break;
+        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<128>, 128, 0); break;
+        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<64>, 64, 0); break;
         case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<false>, kBlock, 0); break;
         default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<true>, kBlock, 0); break;
     }

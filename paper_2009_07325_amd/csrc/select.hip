@@ -227,6 +227,14 @@ template <typename T>
 __device__ __forceinline__ void st_co(T* p, T v) {      // coherent store
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <typename T>
+__device__ __forceinline__ T ld_co(const IMM_GLOBAL T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_co(IMM_GLOBAL T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Grid barrier over all (co-resident) blocks.  Every block first waits for its own memory
 // operations to complete, so once the last block has arrived, everything written before
@@ -267,6 +275,14 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* bar, unsigned int& epoch)
     return s_ok != 0;
 }
 
+// Per-wave staging of one cover batch: exclusive prefix of the newly covered sets' sizes
+// and, per set, its members and its instance's counters.
+struct CoverLds {
+    int32_t pre[kWave + 1];
+    const int32_t* mem[kWave];
+    int32_t* h[kWave];
+};
+
 // Exclusive prefix of one int64 per thread of the block into out[0..blockDim], with
 // out[blockDim] the total.
 __device__ __forceinline__ void block_excl_scan_i64(int64_t v, int64_t* out, int64_t* wsum) {
@@ -293,6 +309,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     __shared__ int64_t ent_beg[kMaxInst];
     __shared__ unsigned long long red[kCoopWaves];
     __shared__ int64_t wsum[kCoopWaves];
+    __shared__ CoverLds cov_all[kCoopWaves];
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     unsigned int epoch = 0;
     // instance prefixes are computed one instance per thread (kMaxInst == kCoopBlock); the
@@ -312,16 +329,17 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             }
             const SelInst& I = inst[lo];
             if (round >= I.k) continue;                  // uniform across the block
-            const int32_t prev = round > 0 ? ld_co(I.seeds + round - 1) : -1;
+            const int32_t prev = round > 0 ? ld_co(global(I.seeds) + round - 1) : -1;
+            IMM_GLOBAL int32_t* h = global(I.h);
             const int64_t base = (t - tile_pre[lo]) * kArgTile;
             unsigned long long best = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t v = base + j * kCoopBlock + tid;
                 if (v < I.n) {
-                    int32_t c = ld_co(I.h + v);
+                    int32_t c = ld_co(h + v);
                     if ((int32_t)v == prev) {
-                        st_co(I.h + v, -1);
+                        st_co(h + v, -1);
                         c = -1;
                     }
                     if (c >= 0) {
@@ -336,7 +354,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             __syncthreads();
             if (tid == 0) {
                 for (int w = 1; w < kCoopWaves; ++w) best = red[w] > best ? red[w] : best;
-                if (best) __hip_atomic_fetch_max(I.keys + round, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (best)
+                    __hip_atomic_fetch_max(global(I.keys) + round, best, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
         }
@@ -345,49 +365,108 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         int64_t cnt = 0;
         if (tid < ninst && round < inst[tid].k) {
             const SelInst& I = inst[tid];
-            const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)ld_co(I.keys + round));
-            const int64_t beg = I.inv_off[u];
+            const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)ld_co(global(I.keys) + round));
+            const int64_t beg = global(I.inv_off)[u];
             ent_beg[tid] = beg;
-            cnt = I.inv_off[u + 1] - beg;
-            if (blockIdx.x == 0) st_co(I.seeds + round, u);
+            cnt = global(I.inv_off)[u + 1] - beg;
+            if (blockIdx.x == 0) st_co(global(I.seeds) + round, u);
         }
         block_excl_scan_i64(cnt, ent_pre, wsum);
         const int64_t nent = ent_pre[ninst];
+        // A wave takes `per` consecutive entries at a time (one per lane, per = 1..64, the
+        // largest power of two that still gives every wave work): those lanes test and mark
+        // their sets' covered flags together, then the members of the newly covered sets
+        // are flattened over the wave (prefix of set sizes in LDS) and decremented four per
+        // lane at a time, so the memory latencies of a batch overlap.
+        CoverLds& C = cov_all[wid];
+        const int64_t ratio = nent / nwaves;
+        const int per = ratio >= 64 ? 64 : ratio >= 1 ? (1 << (63 - __builtin_clzll((unsigned long long)ratio))) : 1;
         unsigned long long mine = 0;
         int mine_inst = -1;
-        for (int64_t e = gwave; e < nent; e += nwaves) {
-            int lo = 0, hi = ninst;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (ent_pre[mid] <= e) lo = mid; else hi = mid;
+        for (int64_t e0 = gwave * per; e0 < nent; e0 += nwaves * per) {
+            const int64_t e = e0 + lane;
+            int li = -1;
+            bool fresh = false;
+            int32_t len = 0;
+            const int32_t* mem = nullptr;
+            int32_t* hh = nullptr;
+            if (lane < per && e < nent) {
+                int lo = 0, hi = ninst;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (ent_pre[mid] <= e) lo = mid; else hi = mid;
+                }
+                li = lo;
+                const SelInst& I = inst[lo];
+                const uint32_t rel = global(I.inv)[ent_beg[lo] + (e - ent_pre[lo])];
+                fresh = ld_co(global(I.covered) + rel) == 0u;
+                if (fresh) {
+                    st_co(global(I.covered) + rel, 1u);
+                    mem = I.ids + global(I.rr_start)[I.first + rel];
+                    len = global(I.rr_len)[I.first + rel];
+                    hh = I.h;
+                }
             }
-            const SelInst& I = inst[lo];
-            const uint32_t rel = I.inv[ent_beg[lo] + (e - ent_pre[lo])];
-            if (ld_co(I.covered + rel)) continue;         // uniform across the wave
-            if (lane == 0) st_co(I.covered + rel, 1u);
-            if (mine_inst != lo) {
-                if (mine && lane == 0) atomic_add_agent(inst[mine_inst].n_covered, mine);
-                mine = 0;
-                mine_inst = lo;
+            // covered counts per instance (an instance's entries are contiguous)
+            uint64_t pending = ballot(fresh);
+            while (pending) {
+                const int x = __builtin_amdgcn_readlane(li, __ffsll((unsigned long long)pending) - 1);
+                const uint64_t mx = ballot(fresh && li == x);
+                if (x != mine_inst) {
+                    if (mine && lane == 0) atomic_add_agent(global(inst[mine_inst].n_covered), mine);
+                    mine = 0;
+                    mine_inst = x;
+                }
+                mine += (unsigned long long)__popcll(mx);
+                pending &= ~mx;
             }
-            ++mine;
-            const int64_t s0 = I.rr_start[I.first + rel];
-            const int32_t len = I.rr_len[I.first + rel];
-            for (int32_t q = lane; q < len; q += kWave)
-                __hip_atomic_fetch_add(I.h + I.ids[s0 + q], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t incl = wave_incl_scan(len);
+            const int32_t total = __shfl(incl, kWave - 1, kWave);
+            if (total == 0) continue;
+            C.pre[lane] = incl - len;
+            C.mem[lane] = mem;
+            C.h[lane] = hh;
+            if (lane == kWave - 1) C.pre[kWave] = incl;
+            wave_sync();
+            for (int32_t q0 = 0; q0 < total; q0 += 4 * kWave) {
+                int32_t v[4];
+                int32_t* hp[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t q = q0 + u * kWave + lane;
+                    hp[u] = nullptr;
+                    if (q < total) {
+                        int lo = 0, hi = per;     // pre[lo] <= q < pre[lo] + len[lo]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (C.pre[mid] <= q) lo = mid; else hi = mid;
+                        }
+                        v[u] = global(C.mem[lo])[q - C.pre[lo]];
+                        hp[u] = C.h[lo];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (hp[u])
+                        __hip_atomic_fetch_add(global(hp[u]) + v[u], -1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+            }
+            wave_sync();
         }
-        if (mine && lane == 0) atomic_add_agent(inst[mine_inst].n_covered, mine);
+        if (mine && lane == 0) atomic_add_agent(global(inst[mine_inst].n_covered), mine);
         if (!grid_sync(bar, epoch)) return;
     }
 }
 
+// One 1024-thread block per CU (16 of the CU's wave slots).  Grids sized at the occupancy
+// limit reported for this kernel (2 blocks per CU) were accepted by the cooperative launch
+// yet not all resident at once for some register allocations, which left the grid barrier
+// waiting; one block per CU keeps a wide margin.
 int select_coop_grid() {
-    int dev = 0, cus = 0, nb = 0;
+    int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_select_coop, kCoopBlock, 0) != hipSuccess || nb < 1)
-        nb = 1;
-    return cus * (nb < 2 ? nb : 2);
+    return cus > 0 ? cus : 1;
 }
 
 int select_max_inst() { return kMaxInst; }
