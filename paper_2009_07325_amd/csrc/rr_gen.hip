@@ -234,27 +234,51 @@ __device__ __forceinline__ uint32_t live_bits(const GraphView& a, uint32_t r, ui
     return bits;
 }
 
+// Ballots of the live edges of group g when all four edges belong to the vertex and share
+// the threshold t (interior groups of a hub vertex with a uniform threshold): the draws go
+// straight into wave masks, with no per-edge range or threshold work.
+__device__ __forceinline__ void live_masks_interior(const GraphView& a, uint32_t r, uint32_t g,
+                                                    uint32_t t, uint64_t m[4]) {
+    const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, a.k0, a.k1);
+    m[0] = ballot(x.x < t);
+    m[1] = ballot(x.y < t);
+    m[2] = ballot(x.z < t);
+    m[3] = ballot(x.w < t);
+}
+
+__device__ __forceinline__ void masks_of_bits(uint32_t bits, uint64_t m[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m[j] = ballot((bits >> j) & 1u);
+}
+
 // Live edges are staged in LDS (edge indices, per wave) and resolved in batches: the
 // source loads and visited test-and-sets of a whole batch are issued together, so the
 // group tests themselves never wait on memory.
 constexpr int kStage = 128;
 
-// Appends the live edges of one pass (bits of group g per lane) to the wave's stage,
-// calling flush() first whenever they would not fit.
+// Appends the live edges of one pass (ballot m[j] of word j of group g per lane) to the
+// wave's stage, calling flush() first whenever they would not fit.
+template <class Flush>
+__device__ __forceinline__ void stage_masks(uint32_t* stage, int32_t& n, const uint64_t m[4],
+                                            uint32_t g, Flush&& flush) {
+    if ((m[0] | m[1] | m[2] | m[3]) == 0) return;
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (m[j] == 0) continue;
+        const int32_t c = (int32_t)__popcll(m[j]);
+        if (n + c > kStage) flush();
+        if ((m[j] >> lane) & 1u) stage[n + (int32_t)lanes_below(m[j])] = (g << 2) + j;
+        n += c;
+    }
+}
+
 template <class Flush>
 __device__ __forceinline__ void stage_edges(uint32_t* stage, int32_t& n, uint32_t bits,
                                             uint32_t g, Flush&& flush) {
-    if (ballot(bits != 0u) == 0) return;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const bool l = (bits >> j) & 1u;
-        const uint64_t m = ballot(l);
-        if (m == 0) continue;
-        const int32_t c = (int32_t)__popcll(m);
-        if (n + c > kStage) flush();
-        if (l) stage[n + (int32_t)lanes_below(m)] = (g << 2) + j;
-        n += c;
-    }
+    uint64_t m[4];
+    masks_of_bits(bits, m);
+    stage_masks(stage, n, m, g, flush);
 }
 
 // Resolves up to 64 staged edges: source of edge stage[i] for i = i0 + lane < n, and
@@ -401,11 +425,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
                 const uint32_t e_end = s0 + (df & kDegMask);
                 const uint32_t g0 = s0 >> 2;
                 const bool uni = (df & kUniformBit) != 0;
+                const bool plain = uni && t0 != kAlways;
                 for (uint32_t base = 0; base < gb && !abandon; base += kWave) {
                     const uint32_t g = g0 + base + lane;
-                    const uint32_t bits =
-                        base + lane < gb ? live_bits(a, r, g, s0, e_end, uni, t0) : 0u;
-                    stage_edges(L.stage, nst, bits, g, flush);
+                    uint64_t m[4];
+                    const int fast = uniform((int)(plain && (base > 0 || (s0 & 3u) == 0) &&
+                                                   base + kWave < gb));
+                    if (fast) {
+                        live_masks_interior(a, r, g, t0, m);   // every lane a full group
+                    } else {
+                        masks_of_bits(base + lane < gb ? live_bits(a, r, g, s0, e_end, uni, t0) : 0u, m);
+                    }
+                    stage_masks(L.stage, nst, m, g, flush);
                 }
             }
 
@@ -573,8 +604,15 @@ __global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenLaunch G) {
                 }
                 const uint32_t q = (c - c_lo) * kWave + lane;
                 const uint32_t g = (bs >> 2) + q;
-                const uint32_t bits = q < gb ? live_bits(a, r, g, bs, be, bu, bt) : 0u;
-                stage_edges(stage, nst, bits, g, flush);
+                uint64_t m[4];
+                const int fast =
+                    uniform((int)(bu && bt != kAlways && (c > c_lo || (bs & 3u) == 0) && c + 1 < c_hi));
+                if (fast) {
+                    live_masks_interior(a, r, g, bt, m);       // every lane a full group
+                } else {
+                    masks_of_bits(q < gb ? live_bits(a, r, g, bs, be, bu, bt) : 0u, m);
+                }
+                stage_masks(stage, nst, m, g, flush);
             }
             // small vertices: windows of kWave groups, each lane searches for its vertex
             for (int32_t base = wid * kWave; base < total_small; base += kHeavyBlock) {
