@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RR sets/s and GTEPS (HBM GB/s vs peak); IMM s/query and p99 batched vs plain"
 
-# Integer-ALU peak of MI355X for Philox4x32-10 (derivation in the design doc): 256 CUs x 64
+# Integer-ALU peak of MI355X for Philox4x32-10: 256 CUs x 64
 # VALU lanes x 2.4 GHz = 39.32e12 lane-cycles/s; one Philox4x32-10 costs 60 lane-cycles
 # (10 rounds x [2 half-rate 32x32->64 multiply-adds = 4, 2 three-input XORs = 2]).
 ALU_LANE_CYCLES = 256 * 64 * 2.4e9
@@ -246,6 +246,105 @@ def bench_batch(args) -> int:
     return 0 if mismatched == 0 else 1
 
 
+# ---------------------------------------------------------------------------------------
+# Served workload: one resident graph, a Poisson stream of IMM queries
+# ---------------------------------------------------------------------------------------
+def bench_serve(args) -> int:
+    import numpy as np
+    import paper_2009_07325_amd as imm
+    from synth import configs
+    t = time.perf_counter()
+    from synth import graphs
+    g, _ = configs.c5_graph(scale=args.c5_scale,
+                            progress=lambda msg: log(f"  graph: {msg} ({time.perf_counter() - t:.0f}s)"))
+    log(f"C5 graph n={g.n} m={g.m} built in {time.perf_counter() - t:.1f}s")
+    # Weighted-cascade IC: with trivalency probabilities every RR set of this graph holds a
+    # giant live component (~2e5 members), so theta * |RR| for eps <= 0.2 exceeds the
+    # device memory by one to three orders of magnitude.
+    p = graphs.weighted_cascade(g)
+    imm.imm_init(0)
+    gg = imm.Graph.from_arrays(g.n, g.in_off, g.in_src, ic_p=p, lt_w=None, lt=True)
+    del p
+    rng = np.random.Generator(np.random.PCG64(5))
+    nq = args.queries
+    qs = [dict(k=int(rng.integers(10, 201)), eps=float(rng.choice([0.2, 0.1, 0.05])),
+               model=int(rng.integers(0, 2))) for _ in range(nq)]
+    gaps = rng.exponential(1.0 / args.qps, nq)
+    seeds = (configs.C5_POOL_SEED_IC, configs.C5_POOL_SEED_LT)
+    srv = imm.imm_server_create(gg.handle, seeds[0], seeds[1], args.hbm_budget_gib << 30,
+                                args.max_active)
+    try:
+        # warm-up: the first queries of each model grow the shared pools
+        for m in (imm.IMM_IC, imm.IMM_LT):
+            tk = imm.imm_server_submit(srv, 50, 0.1, 1.0, m)
+            imm.imm_server_wait(srv, tk, 50)
+        base = imm.imm_server_stats_get(srv)
+        log(f"warm-up done: pools IC {base['pool_sets_ic']} LT {base['pool_sets_lt']} sets")
+        t0 = time.perf_counter()
+        tickets, at = [], 0.0
+        for q, gap in zip(qs, gaps):
+            at += gap
+            delay = t0 + at - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(imm.imm_server_submit(srv, q["k"], q["eps"], 1.0, q["model"]))
+            if len(tickets) % 50 == 0:
+                log(f"  submitted {len(tickets)}/{nq}")
+        results = []
+        for tk, q in zip(tickets, qs):
+            results.append(imm.imm_server_wait(srv, tk, q["k"]))
+            if len(results) % 25 == 0:
+                log(f"  completed {len(results)}/{nq} at {time.perf_counter() - t0:.1f}s")
+        elapsed = time.perf_counter() - t0
+        st = imm.imm_server_stats_get(srv)
+    finally:
+        imm.imm_server_destroy(srv)
+    lat = np.array([i["t_total_s"] for _, i in results])
+    log(f"served {nq} queries in {elapsed:.2f}s; p50 {np.percentile(lat, 50):.3f}s "
+        f"p99 {np.percentile(lat, 99):.3f}s")
+    # one at a time: the first queries of the stream as plain solves
+    nseq = min(args.sequential, nq)
+    t1 = time.perf_counter()
+    mismatched = 0
+    for j in range(nseq):
+        q = qs[j]
+        s_alone, i_alone = imm.imm_solve(gg.handle, q["k"], q["eps"], 1.0, q["model"],
+                                         seeds[q["model"]])
+        mismatched += int(not np.array_equal(s_alone, results[j][0]) or
+                          i_alone["theta"] != results[j][1]["theta"])
+        log(f"  sequential {j + 1}/{nseq}: {time.perf_counter() - t1:.1f}s")
+    t_seq = time.perf_counter() - t1
+    out = {
+        "metric": METRIC,
+        "value": nq / elapsed,
+        "unit": "IMM queries/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 2,
+        "ms_per_step": elapsed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded R-MAT graph, seeded query stream; no dataset)",
+        "config": {"workload": f"C5: R-MAT scale {args.c5_scale} (n={g.n}, m={g.m}), WC IC "
+                               f"and WC-LT; Poisson stream of {nq} queries at {args.qps} QPS, "
+                               "k ~ U{10..200}, eps in {0.2, 0.1, 0.05}, model IC or LT; "
+                               f"{args.max_active} active at most",
+                   "queries": nq, "qps_offered": args.qps},
+        "served": {"queries_s": nq / elapsed, "p50_latency_s": float(np.percentile(lat, 50)),
+                   "p99_latency_s": float(np.percentile(lat, 99)),
+                   "mean_latency_s": float(lat.mean()), "ticks": st["ticks"] - base["ticks"],
+                   "pool_sets_ic": st["pool_sets_ic"], "pool_sets_lt": st["pool_sets_lt"],
+                   "device_bytes": st["device_bytes"]},
+        "sequential": {"queries": nseq, "s_total": t_seq,
+                       "queries_s": nseq / t_seq if t_seq > 0 else None},
+        "results_equal_sequential": mismatched == 0,
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if mismatched == 0 else 1
+
+
 def copy_calibration(nbytes: int, reps: int) -> int:
     """Launches a plain device-to-device copy kernel of known size (torch's elementwise
     copy of nbytes) `reps` times: the reference that scales HBM byte counters read under a
@@ -271,7 +370,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--queries", type=int, default=200, help="c5: queries in the stream")
+    ap.add_argument("--qps", type=float, default=20.0, help="c5: offered queries per second")
+    ap.add_argument("--max-active", type=int, default=16, help="c5: queries in flight at most")
+    ap.add_argument("--hbm-budget-gib", type=int, default=160, help="c5: server memory budget")
+    ap.add_argument("--sequential", type=int, default=20, help="c5: queries also solved alone")
+    ap.add_argument("--c5-scale", type=int, default=24, help="c5: R-MAT scale of the graph")
     ap.add_argument("--instances", type=int, default=256, help="c4: instances of the mix")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -281,7 +386,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one MI355X: this build has no multi-GPU path "
-              "(RR index ranges would shard across GPUs; see DESIGN.md). Use --gpus 1.",
+              "(RR index ranges would shard across GPUs). Use --gpus 1.",
               file=sys.stderr)
         return 2
 
@@ -290,6 +395,9 @@ def main() -> int:
     if args.workload == "c4":
         log("host:", json.dumps(host_info()))
         return bench_batch(args)
+    if args.workload == "c5":
+        log("host:", json.dumps(host_info()))
+        return bench_serve(args)
     import paper_2009_07325_amd as imm
     log("host:", json.dumps(host_info()))
     t = time.perf_counter()

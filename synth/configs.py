@@ -84,8 +84,8 @@ def c4_instance(spec: InstanceSpec) -> Workload:
                     k=spec.k, eps=spec.eps, ell=1.0, seed=spec.pool_seed)
 
 
-def c5_graph(scale: int = 24, edge_factor: int = 16) -> tuple[graphs.Graph, np.ndarray]:
-    g = graphs.rmat(scale, edge_factor << scale, seed=5)
+def c5_graph(scale: int = 24, edge_factor: int = 16, progress=None) -> tuple[graphs.Graph, np.ndarray]:
+    g = graphs.rmat(scale, edge_factor << scale, seed=5, progress=progress)
     return g, graphs.trivalency(g, seed=55)
 
 

@@ -79,18 +79,23 @@ class Graph:
         return np.repeat(np.arange(self.n, dtype=np.int32), self.in_degree())
 
 
-def _distinct(draw, m: int, batch: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+def _distinct(draw, m: int, batch: int, seed: int, progress=None) -> tuple[np.ndarray, np.ndarray]:
     """Draw candidate (src, dst) pairs with ``draw(first, count)`` until at least ``m``
     distinct non-loop pairs exist, then keep a seeded uniform subset of exactly ``m``
-    (the m distinct pairs with the smallest seeded hash)."""
+    (the m distinct pairs with the smallest seeded hash).  ``progress(msg)``, if given, is
+    called after each step."""
     keys = np.zeros(0, dtype=np.int64)
     first = 0
     while True:
         s, d = draw(first, batch)
         first += batch
+        if progress:
+            progress(f"drew {first} candidate edges")
         keep = s != d
         k = s[keep].astype(np.int64) << 32 | d[keep].astype(np.int64)
         keys = np.unique(np.concatenate([keys, k]))
+        if progress:
+            progress(f"{len(keys)} distinct edges")
         if len(keys) >= m:
             break
         # deterministic growth: the next batch size depends only on counts so far
@@ -131,7 +136,7 @@ def erdos_renyi(n: int, m: int, seed: int) -> Graph:
 
 
 def rmat(scale: int, m: int, seed: int, a=0.57, b=0.19, c=0.19, n: int | None = None,
-         permute: bool = True) -> Graph:
+         permute: bool = True, progress=None) -> Graph:
     """R-MAT graph on 2^scale vertex slots with exactly m distinct non-loop edges.
 
     If ``n`` is given (n <= 2^scale), candidate edges with an endpoint >= n are rejected,
@@ -155,11 +160,15 @@ def rmat(scale: int, m: int, seed: int, a=0.57, b=0.19, c=0.19, n: int | None = 
         return src, dst
 
     overdraw = 1.25 if n == nslots else 1.25 * (nslots / n) ** 2
-    src, dst = _distinct(draw, m, int(m * min(overdraw, 64.0)) + 1024, seed)
+    src, dst = _distinct(draw, m, int(m * min(overdraw, 64.0)) + 1024, seed, progress)
     if permute:
         perm = np.random.Generator(np.random.PCG64(seed)).permutation(n).astype(np.int32)
         src, dst = perm[src], perm[dst]
+        if progress:
+            progress("ids permuted")
     in_off, in_src = _to_in_csr(n, src, dst)
+    if progress:
+        progress("in-edge CSR built")
     return Graph(n, in_off, in_src, name=f"rmat_s{scale}_n{n}_m{m}",
                  meta=dict(kind="rmat", scale=scale, seed=seed, abcd=(a, b, c, 1 - a - b - c)))
 
