@@ -51,15 +51,23 @@ struct Ctr4 {
     uint32_t x, y, z, w;
 };
 
-__host__ __device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t k1) {
+// Three-input XOR in one instruction (v_bitop3_b32 with truth table 0x96); the compiler
+// emits two v_xor_b32 for a ^ b ^ c.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+__device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t a = (uint64_t)c.x * 0xD2511F53u;
         const uint64_t b = (uint64_t)c.z * 0xCD9E8D57u;
         Ctr4 o;
-        o.x = (uint32_t)(b >> 32) ^ c.y ^ k0;
+        o.x = xor3((uint32_t)(b >> 32), c.y, k0);
         o.y = (uint32_t)b;
-        o.z = (uint32_t)(a >> 32) ^ c.w ^ k1;
+        o.z = xor3((uint32_t)(a >> 32), c.w, k1);
         o.w = (uint32_t)a;
         c = o;
         k0 += 0x9E3779B9u;
@@ -68,7 +76,7 @@ __host__ __device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t 
     return c;
 }
 
-__host__ __device__ __forceinline__ uint32_t root_of(uint32_t r, uint32_t n, uint32_t k0,
+__device__ __forceinline__ uint32_t root_of(uint32_t r, uint32_t n, uint32_t k0,
                                                      uint32_t k1) {
     Ctr4 w = philox10(Ctr4{r, 0u, 0u, kDomainRoot}, k0, k1);
     return (uint32_t)(((uint64_t)w.x * n) >> 32);

@@ -501,7 +501,7 @@ __device__ __forceinline__ uint64_t block_incl_scan(uint64_t v, uint64_t* wsum) 
 // packed in one 64-bit value (fields of 16, 16 and 32 bits: a batch has at most 1024
 // vertices, each with fewer than kWave groups in the first field).
 template <int kHeavyBlock>
-__global__ __launch_bounds__(kHeavyBlock) void k_ic_heavy(GenLaunch G) {
+__global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ic_heavy(GenLaunch G) {
     constexpr int kHeavyWaves = kHeavyBlock / kWave;
     __shared__ int32_t pre[kHeavyBlock + 1];
     __shared__ uint32_t st[kHeavyBlock], dgs[kHeavyBlock], ths[kHeavyBlock];
