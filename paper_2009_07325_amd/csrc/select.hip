@@ -279,9 +279,53 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* bar, unsigned int& epoch)
 // and, per set, its members and its instance's counters.
 struct CoverLds {
     int32_t pre[kWave + 1];
+    int32_t inst[kWave];
     const int32_t* mem[kWave];
-    int32_t* h[kWave];
 };
+
+// Per-block combining of counter decrements.  In the first rounds the newly covered sets
+// overlap heavily, so the same counters are decremented from many blocks; device-scope
+// atomics on one address serialise across the XCDs.  Each block therefore adds its
+// decrements into an LDS table keyed by (instance, vertex) (open addressing, two probes;
+// a decrement that finds no slot goes straight to the device counter) and applies each
+// slot's total with one device atomic at the end of the cover step.
+constexpr int kDecSlots = 4096;
+constexpr unsigned long long kDecEmpty = ~0ull;
+struct DecCache {
+    unsigned long long key[kDecSlots];
+    int32_t cnt[kDecSlots];
+};
+
+__device__ __forceinline__ void dec_counter(DecCache& dc, const SelInst* inst, int32_t li,
+                                            int32_t v) {
+    const unsigned long long key = ((unsigned long long)(uint32_t)li << 32) | (uint32_t)v;
+    uint32_t slot = (((uint32_t)v * 2654435761u) ^ ((uint32_t)li * 0x9E3779B9u)) >> 20;
+#pragma unroll
+    for (int probe = 0; probe < 2; ++probe) {
+        unsigned long long cur = dc.key[slot];
+        if (cur == kDecEmpty) cur = atomicCAS(&dc.key[slot], kDecEmpty, key);
+        if (cur == kDecEmpty || cur == key) {
+            atomicAdd(&dc.cnt[slot], 1);
+            return;
+        }
+        slot = (slot + 1u) & (kDecSlots - 1u);
+    }
+    __hip_atomic_fetch_add(global(inst[li].h) + v, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Applies and clears the block's table (all threads of the block).
+__device__ __forceinline__ void dec_flush(DecCache& dc, const SelInst* inst) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < kDecSlots; i += blockDim.x) {
+        const unsigned long long key = dc.key[i];
+        if (key != kDecEmpty) {
+            __hip_atomic_fetch_add(global(inst[(int32_t)(key >> 32)].h) + (int32_t)(uint32_t)key,
+                                   -dc.cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            dc.key[i] = kDecEmpty;
+            dc.cnt[i] = 0;
+        }
+    }
+}
 
 // Exclusive prefix of one int64 per thread of the block into out[0..blockDim], with
 // out[blockDim] the total.
@@ -310,14 +354,17 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     __shared__ unsigned long long red[kCoopWaves];
     __shared__ int64_t wsum[kCoopWaves];
     __shared__ CoverLds cov_all[kCoopWaves];
+    __shared__ DecCache dc;
+    for (int i = threadIdx.x; i < kDecSlots; i += blockDim.x) {
+        dc.key[i] = kDecEmpty;
+        dc.cnt[i] = 0;
+    }
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     unsigned int epoch = 0;
     // instance prefixes are computed one instance per thread (kMaxInst == kCoopBlock); the
     // tables past ninst repeat the total
     block_excl_scan_i64(tid < ninst ? (inst[tid].n + kArgTile - 1) / kArgTile : 0, tile_pre, wsum);
     const int64_t ntiles = tile_pre[ninst];
-    const int64_t gwave = (int64_t)blockIdx.x * kCoopWaves + wid;
-    const int64_t nwaves = (int64_t)gridDim.x * kCoopWaves;
 
     for (int32_t round = 0; round < maxk; ++round) {
         // ---- argmax: tiles of kArgTile counters, any instance still selecting ----
@@ -379,6 +426,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         // are flattened over the wave (prefix of set sizes in LDS) and decremented four per
         // lane at a time, so the memory latencies of a batch overlap.
         CoverLds& C = cov_all[wid];
+        const int64_t gwave = (int64_t)blockIdx.x * kCoopWaves + wid;
+        const int64_t nwaves = (int64_t)gridDim.x * kCoopWaves;
         const int64_t ratio = nent / nwaves;
         const int per = ratio >= 64 ? 64 : ratio >= 1 ? (1 << (63 - __builtin_clzll((unsigned long long)ratio))) : 1;
         unsigned long long mine = 0;
@@ -389,7 +438,6 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             bool fresh = false;
             int32_t len = 0;
             const int32_t* mem = nullptr;
-            int32_t* hh = nullptr;
             if (lane < per && e < nent) {
                 int lo = 0, hi = ninst;
                 while (hi - lo > 1) {
@@ -404,7 +452,6 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                     st_co(global(I.covered) + rel, 1u);
                     mem = I.ids + global(I.rr_start)[I.first + rel];
                     len = global(I.rr_len)[I.first + rel];
-                    hh = I.h;
                 }
             }
             // covered counts per instance (an instance's entries are contiguous)
@@ -425,16 +472,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             if (total == 0) continue;
             C.pre[lane] = incl - len;
             C.mem[lane] = mem;
-            C.h[lane] = hh;
+            C.inst[lane] = li;
             if (lane == kWave - 1) C.pre[kWave] = incl;
             wave_sync();
             for (int32_t q0 = 0; q0 < total; q0 += 4 * kWave) {
-                int32_t v[4];
-                int32_t* hp[4];
+                int32_t v[4], vi[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int32_t q = q0 + u * kWave + lane;
-                    hp[u] = nullptr;
+                    vi[u] = -1;
                     if (q < total) {
                         int lo = 0, hi = per;     // pre[lo] <= q < pre[lo] + len[lo]
                         while (hi - lo > 1) {
@@ -442,18 +488,17 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                             if (C.pre[mid] <= q) lo = mid; else hi = mid;
                         }
                         v[u] = global(C.mem[lo])[q - C.pre[lo]];
-                        hp[u] = C.h[lo];
+                        vi[u] = C.inst[lo];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (hp[u])
-                        __hip_atomic_fetch_add(global(hp[u]) + v[u], -1, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                    if (vi[u] >= 0) dec_counter(dc, inst, vi[u], v[u]);
             }
             wave_sync();
         }
         if (mine && lane == 0) atomic_add_agent(global(inst[mine_inst].n_covered), mine);
+        dec_flush(dc, inst);
         if (!grid_sync(bar, epoch)) return;
     }
 }
