@@ -378,6 +378,9 @@ def main() -> int:
     ap.add_argument("--sequential", type=int, default=20, help="c5: queries also solved alone")
     ap.add_argument("--c5-scale", type=int, default=24, help="c5: R-MAT scale of the graph")
     ap.add_argument("--instances", type=int, default=256, help="c4: instances of the mix")
+    ap.add_argument("--autotune", type=int, default=0, metavar="SETS",
+                    help="c1-c3: tune the generation launch on this many pilot sets first "
+                         "(outside the timed region; results do not change)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -407,6 +410,12 @@ def main() -> int:
     model = imm.IMM_IC if w.model == "IC" else imm.IMM_LT
     g = imm.Graph.from_arrays(w.graph.n, w.graph.in_off, w.graph.in_src, ic_p=w.ic_p,
                               lt_w=w.lt_w, lt=(w.model == "LT"))
+
+    tuning = None
+    if args.autotune > 0:
+        t = time.perf_counter()
+        tuning = imm.imm_autotune(g.handle, model, w.seed, args.autotune)
+        log(f"autotune ({time.perf_counter() - t:.1f}s): {json.dumps(tuning)}")
 
     def step():
         return imm.imm_solve(g.handle, w.k, w.eps, w.ell, model, w.seed)
@@ -467,6 +476,7 @@ def main() -> int:
         "t_generate_s": sum(i["t_generate_s"] for i in infos) / args.steps,
         "t_select_s": sum(i["t_select_s"] for i in infos) / args.steps,
         "seeds_head": [int(s) for s in seeds[:5]],
+        "tuning": tuning,
         "roofline": {
             "kernel": dom,
             "bound": "alu",

@@ -175,6 +175,25 @@ imm_status imm_solve(const imm_graph* g, int32_t k, double eps, double ell, imm_
 imm_status imm_solve_pool(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh_final,
                           void* stream, int32_t* seeds_out, imm_info* info);
 
+/* ---- autotuning ---------------------------------------------------------------------
+ * Times the generation of RR sets [0, pilot_sets) of (g, model, seed) under each candidate
+ * launch configuration (light-wave budget of 4-edge groups in {1024 .. 16384}, threads per
+ * heavy set in {128, 256}) and keeps the fastest for pools created on g with that model
+ * afterwards (imm_pool_create, imm_solve, servers; not batches).  RR sets, and therefore
+ * every result, are identical under all configurations (gIM Sec. III-F sizes its blocks
+ * for the same purpose).  The IMM_LIGHT_BUDGET / IMM_HEAVY_BLOCK environment variables
+ * still override.  Not thread-safe with other calls on g. */
+typedef struct {
+    int64_t light_budget;
+    int32_t heavy_block;
+    int32_t candidates;           /* configurations timed */
+    double best_sets_per_s;       /* pilot generation rate of the chosen configuration */
+    double default_sets_per_s;    /* ... of the library default (4096, 256) */
+} imm_tune_info;
+
+imm_status imm_autotune(imm_graph* g, imm_model model, uint64_t seed, int64_t pilot_sets,
+                        imm_tune_info* out);
+
 /* ---- batched solves (many independent instances in shared launches) ---------------------
  * Solves every item as imm_solve(graph, k, eps, ell, model, {seed, fresh_final}) would, with
  * bit-identical seeds and info counters (theta, LB, covered, phases, num_rr).  The

@@ -29,7 +29,8 @@ EXPORTS = ("imm_init", "imm_last_error", "imm_release_cached_memory", "imm_graph
            "imm_graph_info", "imm_graph_export_encoding", "imm_pool_create", "imm_pool_destroy",
            "imm_pool_size", "imm_generate_rr", "imm_rr_export", "imm_rr_histogram",
            "imm_select_seeds", "imm_solve", "imm_solve_pool", "imm_log_binom",
-           "imm_lambda_prime", "imm_lambda_star", "imm_batch_solve", "imm_server_create",
+           "imm_lambda_prime", "imm_lambda_star", "imm_autotune", "imm_batch_solve",
+           "imm_server_create",
            "imm_server_submit",
            "imm_server_poll", "imm_server_wait", "imm_server_stats_get", "imm_server_destroy")
 
@@ -59,6 +60,15 @@ class ImmInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class ImmTuneInfo(ctypes.Structure):
+    _fields_ = [("light_budget", ctypes.c_int64), ("heavy_block", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("best_sets_per_s", ctypes.c_double),
+                ("default_sets_per_s", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class ImmBatchItem(ctypes.Structure):
@@ -124,6 +134,7 @@ def lib() -> ctypes.CDLL:
             "imm_solve": [p, i32, dbl, dbl, ctypes.c_int, ctypes.POINTER(ImmOptions), p,
                           ctypes.POINTER(ImmInfo)],
             "imm_solve_pool": [p, i32, dbl, dbl, i32, p, p, ctypes.POINTER(ImmInfo)],
+            "imm_autotune": [p, ctypes.c_int, u64, i64, ctypes.POINTER(ImmTuneInfo)],
             "imm_batch_solve": [ctypes.POINTER(ImmBatchItem), i32, p,
                                 ctypes.POINTER(ImmBatchStats)],
             "imm_server_create": [p, u64, u64, i64, i32, pp],
@@ -281,6 +292,12 @@ def imm_solve_pool(p, k: int, eps: float, ell: float, fresh_final: bool = False,
     _check(lib().imm_solve_pool(p, k, eps, ell, int(fresh_final), _stream(stream), _ptr(seeds),
                                 ctypes.byref(info)))
     return seeds, info.as_dict()
+
+
+def imm_autotune(g, model: int, seed: int, pilot_sets: int) -> dict:
+    info = ImmTuneInfo()
+    _check(lib().imm_autotune(g, model, seed, pilot_sets, ctypes.byref(info)))
+    return info.as_dict()
 
 
 def imm_batch_solve(items, stream=None, stats: dict | None = None) -> list[tuple[np.ndarray, dict]]:

@@ -337,7 +337,7 @@ static imm_status pool_init(imm_pool* p) {
     IMM_TRY(dalloc(&p->ctr, 1));
     HIP_TRY(hipMemset(p->hist, 0, sizeof(uint32_t) * (size_t)g->n));
     HIP_TRY(hipMemset(p->ctr, 0, sizeof(PoolCounters)));
-    return p->gen.init(g->device, p->model, g->cus);
+    return p->gen.init(g->device, p->model, g->cus, &g->tuned[p->model]);
 }
 
 extern "C" imm_status imm_pool_create(const imm_graph* g, imm_model model, uint64_t seed,

@@ -20,7 +20,7 @@ using namespace imm;
 // ------------------------------------------------------------------------------------
 // GenCtx
 // ------------------------------------------------------------------------------------
-imm_status GenCtx::init(int device_, imm_model model_, int cus_) {
+imm_status GenCtx::init(int device_, imm_model model_, int cus_, const GenTuning* tuning) {
     device = device_;
     model = model_;
     cus = cus_;
@@ -31,6 +31,8 @@ imm_status GenCtx::init(int device_, imm_model model_, int cus_) {
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventCreate(&ev2));
+    if (tuning && tuning->budget > 0) budget = tuning->budget;
+    if (tuning && tuning->heavy_block > 0) heavy_block = tuning->heavy_block;
     if (const char* b = getenv("IMM_LIGHT_BUDGET")) budget = std::max(1ll, atoll(b));
     if (const char* b = getenv("IMM_HEAVY_SCRATCH_GIB"))
         heavy_scratch = std::max(1ll, atoll(b)) << 30;

@@ -134,7 +134,17 @@ struct ImmPlan {
 }  // namespace imm
 
 // ---- library objects -------------------------------------------------------------------
+namespace imm {
+// Generation launch configuration chosen by imm_autotune for one model of a graph (zero:
+// not tuned, library defaults).
+struct GenTuning {
+    int64_t budget = 0;
+    int heavy_block = 0;
+};
+}  // namespace imm
+
 struct imm_graph {
+    imm::GenTuning tuned[2];     // per model
     int device = 0;
     int32_t n = 0;
     int64_t m = 0;
@@ -220,7 +230,9 @@ struct GenCtx {
     double heavy_s = 0.0;               // heavy kernel (IC) / HBM-list walk kernel (LT)
     int64_t heavy_launches = 0;
 
-    imm_status init(int device_, imm_model model_, int cus_);
+    // Defaults, then `tuning` (if given and set), then the IMM_LIGHT_BUDGET /
+    // IMM_HEAVY_BLOCK / IMM_HEAVY_SCRATCH_GIB environment overrides.
+    imm_status init(int device_, imm_model model_, int cus_, const GenTuning* tuning = nullptr);
     int64_t bytes() const;
     void release();
 };
