@@ -128,6 +128,21 @@ imm_status ImmPlan::next(int64_t* gen_upto, int64_t* sel_first, int64_t* sel_cou
     return IMM_OK;
 }
 
+int64_t ImmPlan::need_cov() const {
+    if (final_phase) return 0;
+    // the test below, as a function of the coverage; it is monotone (each operation rounds
+    // monotonically), so the threshold is found by bisection
+    auto pass = [&](int64_t c) { return (double)n * (double)c / (double)used >= (1.0 + ep) * x; };
+    if (!pass(used)) return used + 1;
+    if (pass(0)) return 0;
+    int64_t lo = 0, hi = used;     // !pass(lo), pass(hi)
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (pass(mid)) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
 imm_status ImmPlan::complete(int64_t cov) {
     ++phases;
     covered = cov;
@@ -590,9 +605,11 @@ imm_status imm::select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* 
 }
 
 static imm_status pool_select(imm_pool* p, int64_t first, int64_t count, int32_t k,
-                              int32_t* seeds_out, int64_t* covered_out, hipStream_t s) {
+                              int32_t* seeds_out, int64_t* covered_out, hipStream_t s,
+                              int64_t need = 0) {
     SelInst si;
     IMM_TRY(select_prepare(p, &p->sel, first, count, k, s, &si));
+    si.need = need;
     SelectWs* w = &p->sel;
     IMM_TRY(select_run(&p->launch, &w, &si, 1, s));
     if (seeds_out) memcpy(seeds_out, w->host_seeds, sizeof(int32_t) * (size_t)k);
@@ -626,7 +643,7 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
         const double ta = now_s();
         IMM_TRY(pool_generate(p, upto, s));
         const double tb = now_s();
-        IMM_TRY(pool_select(p, first, count, k, seeds_out, &cov, s));
+        IMM_TRY(pool_select(p, first, count, k, seeds_out, &cov, s, plan.need_cov()));
         t_gen += tb - ta;
         t_sel += now_s() - tb;
         IMM_TRY(plan.complete(cov));

@@ -125,6 +125,7 @@ extern "C" imm_status imm_batch_solve(imm_batch_item* items, int32_t count, void
             Inst& x = inst[(size_t)act[j]];
             ws[j] = &x.pool->sel;
             st = select_prepare(x.pool, ws[j], x.sel_first, x.sel_count, x.item->k, s, &si[j]);
+            si[j].need = x.plan.need_cov();
         }
         if (st == IMM_OK) st = select_run(&launch, ws.data(), si.data(), (int32_t)act.size(), s);
         if (st != IMM_OK) break;

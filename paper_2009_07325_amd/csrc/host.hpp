@@ -125,6 +125,9 @@ struct ImmPlan {
     imm_status init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_);
     imm_status next(int64_t* gen_upto, int64_t* sel_first, int64_t* sel_count);
     imm_status complete(int64_t cov);
+    // Smallest coverage of the current estimation phase's selection that passes its test
+    // (used + 1 when none does); 0 in the final phase.
+    int64_t need_cov() const;
     double spread_est() const { return (double)n * (double)covered / (double)(upto - first); }
 
   private:

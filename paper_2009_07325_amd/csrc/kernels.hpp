@@ -144,6 +144,11 @@ struct SelInst {
     unsigned long long* keys;      // k argmax keys (zeroed)
     int32_t* seeds;                // k
     unsigned long long* n_covered; // zeroed
+    // Estimation phases: the smallest coverage that passes the phase's test.  Greedy gains
+    // never increase, so once (covered so far) + (rounds left) x (this round's gain) falls
+    // below it the phase fails whatever the remaining seeds are, and the instance stops.
+    // 0: always run all k rounds.
+    int64_t need;
 };
 // Arrival counters of a hierarchical grid barrier (zeroed before each launch): block b
 // arrives on sub[b % 16]; the last arrival of a group bumps top; all wait for top.

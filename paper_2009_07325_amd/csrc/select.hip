@@ -355,10 +355,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     __shared__ int64_t wsum[kCoopWaves];
     __shared__ CoverLds cov_all[kCoopWaves];
     __shared__ DecCache dc;
+    __shared__ unsigned char stopped[kMaxInst];   // estimation phase decided (failed)
     for (int i = threadIdx.x; i < kDecSlots; i += blockDim.x) {
         dc.key[i] = kDecEmpty;
         dc.cnt[i] = 0;
     }
+    if (threadIdx.x < kMaxInst) stopped[threadIdx.x] = 0;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     unsigned int epoch = 0;
     // instance prefixes are computed one instance per thread (kMaxInst == kCoopBlock); the
@@ -367,6 +369,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     const int64_t ntiles = tile_pre[ninst];
 
     for (int32_t round = 0; round < maxk; ++round) {
+        // coverage after the previous rounds (nothing adds to it before the next barrier);
+        // thread i keeps instance i's
+        const int64_t cov_before = tid < ninst ? (int64_t)ld_co(global(inst[tid].n_covered)) : 0;
         // ---- argmax: tiles of kArgTile counters, any instance still selecting ----
         for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
             int lo = 0, hi = ninst;                      // tile_pre[lo] <= t < tile_pre[hi]
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 if (tile_pre[mid] <= t) lo = mid; else hi = mid;
             }
             const SelInst& I = inst[lo];
-            if (round >= I.k) continue;                  // uniform across the block
+            if (round >= I.k || stopped[lo]) continue;   // uniform across the block
             const int32_t prev = round > 0 ? ld_co(global(I.seeds) + round - 1) : -1;
             IMM_GLOBAL int32_t* h = global(I.h);
             const int64_t base = (t - tile_pre[lo]) * kArgTile;
@@ -409,15 +414,27 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         }
         if (!grid_sync(bar, epoch)) return;
         // ---- cover: sets containing each instance's new seed ----
+        // Every block reads the same final keys and coverage, so every block takes the same
+        // stop decisions.
         int64_t cnt = 0;
-        if (tid < ninst && round < inst[tid].k) {
+        bool live = false;
+        if (tid < ninst && round < inst[tid].k && !stopped[tid]) {
             const SelInst& I = inst[tid];
-            const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)ld_co(global(I.keys) + round));
-            const int64_t beg = global(I.inv_off)[u];
-            ent_beg[tid] = beg;
-            cnt = global(I.inv_off)[u + 1] - beg;
-            if (blockIdx.x == 0) st_co(global(I.seeds) + round, u);
+            const unsigned long long key = ld_co(global(I.keys) + round);
+            const int64_t gain = key ? (int64_t)(key >> 32) - 1 : 0;
+            const int64_t bound = cov_before + (int64_t)(I.k - round) * gain;
+            if (I.need > 0 && bound < I.need) {
+                stopped[tid] = 1;
+            } else {
+                live = true;
+                const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
+                const int64_t beg = global(I.inv_off)[u];
+                ent_beg[tid] = beg;
+                cnt = global(I.inv_off)[u + 1] - beg;
+                if (blockIdx.x == 0) st_co(global(I.seeds) + round, u);
+            }
         }
+        if (!__syncthreads_or(live)) return;            // every instance finished or stopped
         block_excl_scan_i64(cnt, ent_pre, wsum);
         const int64_t nent = ent_pre[ninst];
         // A wave takes `per` consecutive entries at a time (one per lane, per = 1..64, the

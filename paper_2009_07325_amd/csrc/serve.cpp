@@ -226,6 +226,7 @@ bool tick(imm_server* S) {
         ws[i] = &S->slots[q.slot];
         imm_status st = select_prepare(S->pools[q.model], ws[i], q.sel_first, q.sel_count, q.k,
                                        S->stream, &inst[i]);
+        inst[i].need = q.plan.need_cov();
         if (st != IMM_OK) {
             std::lock_guard<std::mutex> lk(S->mu);
             S->worker_status = st;
