@@ -152,7 +152,10 @@ imm_status ImmPlan::complete(int64_t cov) {
     }
     if ((double)n * (double)cov / (double)used >= (1.0 + ep) * x) {
         lb = (double)n * (double)cov / (double)used / (1.0 + ep);
-        return enter_final();
+        IMM_TRY(enter_final());
+        // a passing phase ran all k rounds over [0, used)
+        reuse = first == 0 && upto == used;
+        return IMM_OK;
     }
     if (++i > rounds) return enter_final();
     return IMM_OK;
@@ -638,6 +641,10 @@ static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_
     ImmPlan plan;
     IMM_TRY(plan.init(p->g->n, k, eps, ell, fresh));
     while (!plan.done) {
+        if (plan.reuses_last()) {          // seeds_out holds that phase's seeds
+            IMM_TRY(plan.complete(plan.covered));
+            continue;
+        }
         int64_t upto, first, count, cov = 0;
         IMM_TRY(plan.next(&upto, &first, &count));
         const double ta = now_s();

@@ -118,16 +118,20 @@ extern "C" imm_status imm_batch_solve(imm_batch_item* items, int32_t count, void
         }
         if (st != IMM_OK) break;
         const double tb = now_s();
-        // 3. all greedy selections in one cooperative launch
-        si.assign(act.size(), SelInst{});
-        ws.assign(act.size(), nullptr);
+        // 3. all greedy selections in one cooperative launch (an instance whose final
+        //    selection repeats its last one keeps that one's seeds and coverage)
+        si.clear();
+        ws.clear();
         for (size_t j = 0; j < act.size() && st == IMM_OK; ++j) {
             Inst& x = inst[(size_t)act[j]];
-            ws[j] = &x.pool->sel;
-            st = select_prepare(x.pool, ws[j], x.sel_first, x.sel_count, x.item->k, s, &si[j]);
-            si[j].need = x.plan.need_cov();
+            if (x.plan.reuses_last()) continue;
+            ws.push_back(&x.pool->sel);
+            si.emplace_back();
+            st = select_prepare(x.pool, ws.back(), x.sel_first, x.sel_count, x.item->k, s, &si.back());
+            si.back().need = x.plan.need_cov();
         }
-        if (st == IMM_OK) st = select_run(&launch, ws.data(), si.data(), (int32_t)act.size(), s);
+        if (st == IMM_OK && !si.empty())
+            st = select_run(&launch, ws.data(), si.data(), (int32_t)si.size(), s);
         if (st != IMM_OK) break;
         const double tc = now_s();
         bs.t_generate_s += tb - ta;

@@ -121,6 +121,10 @@ struct ImmPlan {
     int64_t theta = 0, first = 0, upto = 0;
     int32_t phases = 0;
     int64_t covered = 0;
+    // The final selection would run on exactly the sets of the estimation phase that passed
+    // (no fresh sample and theta within the sets already drawn): greedy is deterministic,
+    // so that phase's seeds and coverage are the final ones and no selection is run.
+    bool reuse = false;
 
     imm_status init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_);
     imm_status next(int64_t* gen_upto, int64_t* sel_first, int64_t* sel_count);
@@ -128,6 +132,7 @@ struct ImmPlan {
     // Smallest coverage of the current estimation phase's selection that passes its test
     // (used + 1 when none does); 0 in the final phase.
     int64_t need_cov() const;
+    bool reuses_last() const { return final_phase && reuse; }
     double spread_est() const { return (double)n * (double)covered / (double)(upto - first); }
 
   private:

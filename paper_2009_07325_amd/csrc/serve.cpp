@@ -218,15 +218,18 @@ bool tick(imm_server* S) {
     }
     if (act.empty()) return true;
     // 3. all selections in one cooperative launch
+    //    (a query whose final selection repeats its last one keeps that one's result)
     const double t0 = now_s();
-    std::vector<SelInst> inst(act.size());
-    std::vector<SelectWs*> ws(act.size());
+    std::vector<SelInst> inst;
+    std::vector<SelectWs*> ws;
     for (size_t i = 0; i < act.size(); ++i) {
         Query& q = act[i];
-        ws[i] = &S->slots[q.slot];
-        imm_status st = select_prepare(S->pools[q.model], ws[i], q.sel_first, q.sel_count, q.k,
-                                       S->stream, &inst[i]);
-        inst[i].need = q.plan.need_cov();
+        if (q.plan.reuses_last()) continue;
+        ws.push_back(&S->slots[q.slot]);
+        inst.emplace_back();
+        imm_status st = select_prepare(S->pools[q.model], ws.back(), q.sel_first, q.sel_count, q.k,
+                                       S->stream, &inst.back());
+        inst.back().need = q.plan.need_cov();
         if (st != IMM_OK) {
             std::lock_guard<std::mutex> lk(S->mu);
             S->worker_status = st;
@@ -234,7 +237,9 @@ bool tick(imm_server* S) {
             return false;
         }
     }
-    imm_status st = select_run(&S->launch, ws.data(), inst.data(), (int32_t)act.size(), S->stream);
+    imm_status st = inst.empty() ? IMM_OK
+                                 : select_run(&S->launch, ws.data(), inst.data(), (int32_t)inst.size(),
+                                              S->stream);
     const double dt = now_s() - t0;
     if (st != IMM_OK) {
         std::lock_guard<std::mutex> lk(S->mu);
