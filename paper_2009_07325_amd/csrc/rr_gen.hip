@@ -234,9 +234,8 @@ __device__ __forceinline__ uint32_t live_bits(const GraphView& a, uint32_t r, ui
     return bits;
 }
 
-// Ballots of the live edges of group g when all four edges belong to the vertex and share
-// the threshold t (interior groups of a hub vertex with a uniform threshold): the draws go
-// straight into wave masks, with no per-edge range or threshold work.
+// Ballots of the draws of group g below the threshold t, one mask per word (the edges of a
+// vertex with one threshold for its whole in-list): no per-edge range or threshold work.
 __device__ __forceinline__ void live_masks_interior(const GraphView& a, uint32_t r, uint32_t g,
                                                     uint32_t t, uint64_t m[4]) {
     const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, a.k0, a.k1);
@@ -244,6 +243,25 @@ __device__ __forceinline__ void live_masks_interior(const GraphView& a, uint32_t
     m[1] = ballot(x.y < t);
     m[2] = ballot(x.z < t);
     m[3] = ballot(x.w < t);
+}
+
+// Lanes [lo, hi) of a wave as a mask (0 <= lo <= hi <= 64).
+__device__ __forceinline__ uint64_t lane_range(uint32_t lo, uint32_t hi) {
+    const uint64_t below_hi = hi >= 64u ? ~0ull : (1ull << hi) - 1ull;
+    return below_hi & ~((1ull << lo) - 1ull);
+}
+
+// Lanes L of a wave whose edge e0 + 4L + j lies in [s, e) (wave-uniform arguments):
+// in[j] for word j.
+__device__ __forceinline__ void edge_range_masks(uint32_t e0, uint32_t s, uint32_t e,
+                                                 uint64_t in[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t ej = e0 + (uint32_t)j;
+        const uint32_t lo = s > ej ? (s - ej + 3u) >> 2 : 0u;
+        const uint32_t hi = e > ej ? min((e - ej + 3u) >> 2, 64u) : 0u;
+        in[j] = lo < hi ? lane_range(lo, hi) : 0ull;
+    }
 }
 
 __device__ __forceinline__ void masks_of_bits(uint32_t bits, uint64_t m[4]) {
@@ -514,7 +532,8 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
     __shared__ uint32_t s_nchunks;
     __shared__ unsigned int s_idx;
     __shared__ unsigned long long s_base;
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const int tid = threadIdx.x, lane = lane_id();
+    const int wid = uniform(tid / kWave);
     const int64_t slot = blockIdx.x;
     uint32_t* vis = G.hvisited + slot * G.vis_words;
     int32_t* list = G.hlist + slot * G.list_stride;
@@ -602,15 +621,25 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
                     bt = uniform(bth[k]);
                     gb = uniform(bng[k]);
                 }
-                const uint32_t q = (c - c_lo) * kWave + lane;
-                const uint32_t g = (bs >> 2) + q;
+                const uint32_t q0 = (c - c_lo) * kWave;        // chunk's first group, relative
+                const uint32_t g = (bs >> 2) + q0 + (uint32_t)lane;
                 uint64_t m[4];
-                const int fast =
-                    uniform((int)(bu && bt != kAlways && (c > c_lo || (bs & 3u) == 0) && c + 1 < c_hi));
-                if (fast) {
-                    live_masks_interior(a, r, g, bt, m);       // every lane a full group
+                if (bu) {
+                    // One threshold for the whole list: the draws go straight into wave
+                    // masks; only the vertex's first and last chunks need the lanes whose
+                    // edges lie outside the list masked off.
+                    uint64_t in[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+                    if (c == c_lo || c + 1 == c_hi) edge_range_masks(((bs >> 2) + q0) << 2, bs, be, in);
+                    if (bt == kAlways) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) m[j] = in[j];
+                    } else {
+                        live_masks_interior(a, r, g, bt, m);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) m[j] &= in[j];
+                    }
                 } else {
-                    masks_of_bits(q < gb ? live_bits(a, r, g, bs, be, bu, bt) : 0u, m);
+                    masks_of_bits(q0 + (uint32_t)lane < gb ? live_bits(a, r, g, bs, be, false, 0u) : 0u, m);
                 }
                 stage_masks(stage, nst, m, g, flush);
             }
