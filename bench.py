@@ -25,11 +25,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RR sets/s and GTEPS (HBM GB/s vs peak); IMM s/query and p99 batched vs plain"
 
-# Integer-ALU peak of MI355X for Philox4x32-10: 256 CUs x 64
-# VALU lanes x 2.4 GHz = 39.32e12 lane-cycles/s; one Philox4x32-10 costs 60 lane-cycles
-# (10 rounds x [2 half-rate 32x32->64 multiply-adds = 4, 2 three-input XORs = 2]).
+# Integer-ALU peak of MI355X for Philox4x32-10: 256 CUs x 64 VALU lanes x 2.4 GHz =
+# 39.32e12 lane-cycles/s; one Philox4x32-10 is 10 rounds x (2 32x32->64 multiply-adds +
+# 2 three-input XORs) = 40 VALU instructions, each one lane-cycle per lane (the 64-bit
+# multiply-add issues at full rate on this chip).
 ALU_LANE_CYCLES = 256 * 64 * 2.4e9
-PHILOX_LANE_CYCLES = 60.0
+PHILOX_LANE_CYCLES = 40.0
 PEAK_GPHILOX = ALU_LANE_CYCLES / PHILOX_LANE_CYCLES / 1e9
 
 
