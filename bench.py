@@ -32,6 +32,8 @@ METRIC = "RR sets/s and GTEPS (HBM GB/s vs peak); IMM s/query and p99 batched vs
 ALU_LANE_CYCLES = 256 * 64 * 2.4e9
 PHILOX_LANE_CYCLES = 40.0
 PEAK_GPHILOX = ALU_LANE_CYCLES / PHILOX_LANE_CYCLES / 1e9
+HBM_PEAK_GBS = 8000.0
+LT_STEP_BYTES = 32.0     # per LT walk step: vertex record 16 + threshold 4 + source 4 + id 4 + histogram 4
 
 
 def log(*a):
@@ -454,6 +456,39 @@ def main() -> int:
                       "ms_per_solve": v[1] / args.steps * 1e3, "launches": v[2]}
                   for k, v in kern.items()}
     gen_all = sum(v[0] for v in kern.values()) / sum(v[1] for v in kern.values()) / 1e9
+    roofline = {
+        "kernel": dom,
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": PEAK_GPHILOX,
+        "unit": "Gphilox/s",
+        "frac": achieved / PEAK_GPHILOX,
+        "traffic": traffic_from_profile(dom, args.workload),
+        "avg_launch_ms": k_time / k_launch * 1e3,
+        "philox_per_launch": philox / max(k_launch, 1),
+        "per_kernel": per_kernel,
+        "generation_gphilox_s": gen_all,
+    }
+    if model == imm.IMM_LT:
+        # LT walks (k_rr_lt, both launch kinds): one step per member, whose algorithmic
+        # bytes are its vertex record, one cumulative threshold, one source, its id and
+        # its histogram entry; the walk is a chain of dependent loads (latency-bound)
+        lt_bytes = sum(i["pool_ids"] for i in infos) * LT_STEP_BYTES
+        lt_time = sum(i["t_rr_kernel_s"] + i["t_rr_heavy_s"] for i in infos)
+        lt_launch = sum(i["rr_kernel_launches"] + i["rr_heavy_launches"] for i in infos)
+        lt_gbs = lt_bytes / lt_time / 1e9 if lt_time > 0 else 0.0
+        roofline = {
+            "kernel": "k_rr_lt",
+            "bound": "hbm",
+            "achieved": lt_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": lt_gbs / HBM_PEAK_GBS,
+            "traffic": traffic_from_profile("k_rr_lt", args.workload),
+            "avg_launch_ms": lt_time / max(lt_launch, 1) * 1e3,
+            "bytes_per_launch": lt_bytes / max(lt_launch, 1),
+            "steps_per_s": sum(i["pool_ids"] for i in infos) / lt_time if lt_time > 0 else 0.0,
+        }
     last = infos[-1]
     out = {
         "metric": METRIC,
@@ -478,19 +513,7 @@ def main() -> int:
         "t_select_s": sum(i["t_select_s"] for i in infos) / args.steps,
         "seeds_head": [int(s) for s in seeds[:5]],
         "tuning": tuning,
-        "roofline": {
-            "kernel": dom,
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_GPHILOX,
-            "unit": "Gphilox/s",
-            "frac": achieved / PEAK_GPHILOX,
-            "traffic": traffic_from_profile(dom, args.workload),
-            "avg_launch_ms": k_time / k_launch * 1e3,
-            "philox_per_launch": philox / max(k_launch, 1),
-            "per_kernel": per_kernel,
-            "generation_gphilox_s": gen_all,
-        },
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample ...")

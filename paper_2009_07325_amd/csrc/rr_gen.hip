@@ -624,6 +624,18 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
                 const uint32_t q0 = (c - c_lo) * kWave;        // chunk's first group, relative
                 const uint32_t g = (bs >> 2) + q0 + (uint32_t)lane;
                 uint64_t m[4];
+                if (bu && bt != kAlways && c > c_lo && c + 1 < c_hi) {
+                    // The wave's interior chunks of this vertex (every edge of every lane in
+                    // the list, one threshold): a tight loop of draws and ballots, with the
+                    // scalar work per chunk cut to the loop control and the live-edge test.
+                    uint32_t gi = g;
+                    for (; c + 1 < c_hi; c += kHeavyWaves, gi += (uint32_t)(kHeavyWaves * kWave)) {
+                        live_masks_interior(a, r, gi, bt, m);
+                        stage_masks(stage, nst, m, gi, flush);
+                    }
+                    c -= kHeavyWaves;                  // the loop increment steps past it
+                    continue;
+                }
                 if (bu) {
                     // One threshold for the whole list: the draws go straight into wave
                     // masks; only the vertex's first and last chunks need the lanes whose
