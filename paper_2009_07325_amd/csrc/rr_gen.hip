@@ -334,20 +334,52 @@ __device__ __forceinline__ void flush_light(const GraphView& a, uint32_t* stage,
     wave_sync();
 }
 
-// Heavy kernel: appends to the workgroup's HBM list (positions from an LDS counter).
+// Vertex records of the most recently queued members of a heavy set, by list position
+// modulo kRing: filled when a member is found, read when its batch starts, so a batch does
+// not wait for its vertices' list entries and records.  Valid for positions [head, size)
+// while size - head <= kRing (no later member has reused the slot yet).
+constexpr int kRing = 512;
+struct RecRing {
+    uint32_t start[kRing];
+    uint32_t deg[kRing];
+    uint32_t thr[kRing];
+};
+
+__device__ __forceinline__ void ring_put(RecRing& ring, int32_t p, const VRec& rec) {
+    const int32_t s = p & (kRing - 1);
+    ring.start[s] = (uint32_t)rec.start;
+    ring.deg[s] = rec.deg;
+    ring.thr[s] = rec.thr;
+}
+
+// Heavy kernel: appends to the workgroup's HBM list (positions from an LDS counter) and
+// puts each new member's vertex record in the ring.  The record is loaded for every
+// resolved edge, in parallel with its test-and-set, so the two waits overlap.
 __device__ __forceinline__ void flush_block(const GraphView& a, uint32_t* stage, int32_t& n,
-                                            int32_t* list, int32_t* s_size, uint32_t* vis) {
+                                            int32_t* list, int32_t* s_size, uint32_t* vis,
+                                            RecRing& ring) {
     wave_sync();
     for (int32_t i0 = 0; i0 < n; i0 += kWave) {
+        const int32_t i = i0 + lane_id();
         int32_t u = 0;
-        const bool fresh = resolve_staged(a, stage, i0, n, vis, u);
+        VRec rec{};
+        bool fresh = false;
+        if (i < n) {
+            u = a.src[stage[i]];
+            rec = load_vrec(a.vrec + u);
+            fresh = vis_test_and_set(vis, u);
+        }
         const uint64_t m = ballot(fresh);
         const int32_t c = (int32_t)__popcll(m);
         if (c == 0) continue;
         int32_t at = 0;
         if (lane_id() == 0) at = atomicAdd(s_size, c);
         at = __shfl(at, 0, kWave);
-        if (fresh) list[at + (int32_t)lanes_below(m)] = u;
+        if (fresh) {
+            const int32_t p = at + (int32_t)lanes_below(m);
+            list[p] = u;
+            ring_put(ring, p, rec);
+        }
     }
     n = 0;
     wave_sync();
@@ -526,6 +558,7 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
     __shared__ uint32_t bst[kHeavyBlock], bdg[kHeavyBlock], bth[kHeavyBlock], bng[kHeavyBlock];
     __shared__ uint32_t bcp[kHeavyBlock + 1];
     __shared__ uint32_t stage_all[kHeavyWaves][kStage];
+    __shared__ RecRing ring;
     __shared__ uint64_t wsum[kHeavyWaves];
     __shared__ unsigned long long wred[kHeavyWaves];
     __shared__ int32_t s_size;
@@ -551,6 +584,7 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
         if (tid == 0) {
             const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, a.k0, a.k1);
             list[0] = root;
+            ring_put(ring, 0, load_vrec(a.vrec + root));
             vis_test_and_set(vis, root);
             s_size = 1;
         }
@@ -561,11 +595,18 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
             const int32_t nb = min(size - head, kHeavyBlock);
             uint32_t ng = 0, dg = 0, s0 = 0, dgf = 0, t0 = 0;
             if (tid < nb) {
-                const VRec rec = load_vrec(a.vrec + list[head + tid]);
-                dgf = rec.deg;
-                t0 = rec.thr;
+                if (size - head <= kRing) {
+                    const int32_t p = (head + tid) & (kRing - 1);
+                    s0 = ring.start[p];
+                    dgf = ring.deg[p];
+                    t0 = ring.thr[p];
+                } else {
+                    const VRec rec = load_vrec(a.vrec + list[head + tid]);
+                    dgf = rec.deg;
+                    t0 = rec.thr;
+                    s0 = (uint32_t)rec.start;
+                }
                 dg = dgf & kDegMask;
-                s0 = (uint32_t)rec.start;
                 ng = groups_of(s0, dg);
             }
             const bool big = ng >= (uint32_t)kWave;
@@ -601,7 +642,7 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
             const uint32_t nchunks = uniform(s_nchunks);
             const int32_t total_small = uniform(pre[nb]);
             int32_t nst = 0;
-            auto flush = [&]() { flush_block(a, stage, nst, list, &s_size, vis); };
+            auto flush = [&]() { flush_block(a, stage, nst, list, &s_size, vis, ring); };
             // big vertices: chunk c -> the vertex k with bcp[k] <= c < bcp[k + 1]; a wave's
             // chunks increase, so its vertex index only moves forward
             uint32_t k = ~0u, c_lo = 0, c_hi = 0;   // chunks [c_lo, c_hi) are vertex k's
@@ -630,8 +671,17 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
                     // scalar work per chunk cut to the loop control and the live-edge test.
                     uint32_t gi = g;
                     for (; c + 1 < c_hi; c += kHeavyWaves, gi += (uint32_t)(kHeavyWaves * kWave)) {
-                        live_masks_interior(a, r, gi, bt, m);
-                        stage_masks(stage, nst, m, gi, flush);
+                        const Ctr4 x = philox10(Ctr4{r, gi, 0u, kDomainIC}, a.k0, a.k1);
+                        // one compare for "any live edge in the wave"; the per-word
+                        // ballots only when there is one (rare on hub vertices)
+                        const uint32_t lo = min(min(x.x, x.y), min(x.z, x.w));
+                        if (ballot(lo < bt) != 0) {
+                            m[0] = ballot(x.x < bt);
+                            m[1] = ballot(x.y < bt);
+                            m[2] = ballot(x.z < bt);
+                            m[3] = ballot(x.w < bt);
+                            stage_masks(stage, nst, m, gi, flush);
+                        }
                     }
                     c -= kHeavyWaves;                  // the loop increment steps past it
                     continue;
