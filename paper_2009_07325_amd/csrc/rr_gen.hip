@@ -818,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
         int32_t v = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
         if (lane == 0) {
             list[0] = v;
-            vis_test_and_set(vis, v);
+            if (kBig) vis_test_and_set(vis, v);
         }
         int32_t size = 1;
         uint64_t examined = 0;
@@ -833,12 +833,20 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
             if (j < 0) break;
             const int32_t u = a.src[j];
             bool fresh = false;
-            if (lane == 0) fresh = vis_test_and_set(vis, u);
-            fresh = __shfl(fresh, 0, kWave);
+            if (kBig) {
+                if (lane == 0) fresh = vis_test_and_set(vis, u);
+                fresh = __shfl(fresh, 0, kWave);
+            } else {
+                // the walk so far is the wave's LDS list: a revisit is a match in it
+                bool seen = false;
+                wave_sync();
+                for (int32_t i = lane; i < size; i += kWave) seen |= list[i] == u;
+                fresh = ballot(seen) == 0;
+            }
             if (!fresh) break;
             if (size + 1 > cap) {
                 abandon = true;
-                if (lane == 0) vis_clear(vis, u);
+                if (kBig && lane == 0) vis_clear(vis, u);
                 break;
             }
             if (lane == 0) list[size] = u;
@@ -848,8 +856,10 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
         if (kBig) __threadfence(); else wave_sync();
         if (abandon) push_heavy(G, ws, inst, r);
         else place_wave(G, ws, slot, inst, r, list, size, examined);
-        for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
-        vis_fence();
+        if (kBig) {
+            for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
+            vis_fence();
+        }
         wave_sync();
     }
     wave_exit(G, ws, slot);
