@@ -772,9 +772,12 @@ __device__ __forceinline__ bool lt_hit(const GraphView& a, int64_t j, uint32_t x
 }
 
 // First j in [s, e) whose cumulative threshold is above the draw (a saturated entry always
-// qualifies), or -1.  The predicate is monotone in j because cum is non-decreasing within
-// an in-list, so a 64-ary search narrows [lo, hi) by a factor of 65 per step.
-__device__ __forceinline__ int64_t lt_pick(const GraphView& a, int64_t s, int64_t e, uint32_t x) {
+// qualifies), or -1; *u is its source.  The predicate is monotone in j because cum is
+// non-decreasing within an in-list, so a 64-ary search narrows [lo, hi) by a factor of 65
+// per step.  The last probe loads each lane's source with its threshold, so the chosen
+// source needs no separate dependent load.
+__device__ __forceinline__ int64_t lt_pick(const GraphView& a, int64_t s, int64_t e, uint32_t x,
+                                           int32_t* u) {
     const int lane = lane_id();
     int64_t lo = s, hi = e;      // the answer lies in [lo, hi]; hi is a hit iff hi_hit
     bool hi_hit = false;
@@ -794,9 +797,23 @@ __device__ __forceinline__ int64_t lt_pick(const GraphView& a, int64_t s, int64_
         }
     }
     const int64_t j = lo + lane;
-    const uint64_t m = ballot(j < hi && lt_hit(a, j, x));
-    if (m != 0) return lo + (__ffsll((unsigned long long)m) - 1);
-    return hi_hit ? hi : -1;
+    int32_t sj = 0;
+    bool hit = false;
+    if (j < hi) {
+        sj = a.src[j];
+        hit = lt_hit(a, j, x);
+    }
+    const uint64_t m = ballot(hit);
+    if (m != 0) {
+        const int f = __ffsll((unsigned long long)m) - 1;
+        *u = __shfl(sj, f, kWave);
+        return lo + f;
+    }
+    if (hi_hit) {
+        *u = a.src[hi];
+        return hi;
+    }
+    return -1;
 }
 
 template <bool kBig>
@@ -829,9 +846,9 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
             if (d == 0) break;
             examined += d;
             const uint32_t x = philox10(Ctr4{r, (uint32_t)v, 0u, kDomainLT}, k0, k1).x;
-            const int64_t j = lt_pick(a, rec.start, rec.start + d, x);
+            int32_t u = 0;
+            const int64_t j = lt_pick(a, rec.start, rec.start + d, x, &u);
             if (j < 0) break;
-            const int32_t u = a.src[j];
             bool fresh = false;
             if (kBig) {
                 if (lane == 0) fresh = vis_test_and_set(vis, u);
