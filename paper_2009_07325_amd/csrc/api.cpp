@@ -470,24 +470,33 @@ extern "C" imm_status imm_rr_histogram(const imm_pool* pc, int64_t first, int64_
 int64_t SelectWs::bytes() const {
     int64_t b = 0;
     if (h) b += n * (4 + 4 + 8 + 4) + 8;
-    b += cap_inv * 4 + cap_cov * 4 + cap_k * 12;
+    for (const IndexSeg& x : seg) b += x.off ? (n + 1) * 8 + x.cap * 4 : 0;
+    if (snap) b += n * 4;
+    b += cap_cov * 4 + cap_k * 12;
     return b;
 }
 
 void SelectWs::release() {
     dfree(h);
     dfree(hist_tmp);
-    dfree(inv_off);
+    for (IndexSeg& x : seg) {
+        dfree(x.off);
+        dfree(x.inv);
+        x.cap = 0;
+    }
+    nseg = 0;
+    ix_pool = nullptr;
+    snap_valid = false;
+    dfree(snap);
     dfree(scan_tmp);
     dfree(cursor);
-    dfree(inv);
     dfree(covered);
     dfree(keys);
     dfree(seeds);
     dfree(n_covered);
     hfree(host_seeds);
     hfree(host_cov);
-    cap_inv = cap_cov = cap_k = 0;
+    cap_cov = cap_k = 0;
 }
 
 void SelectLaunch::release() {
@@ -508,18 +517,10 @@ static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t
     if (!w->h) {
         w->n = n;
         IMM_TRY(dalloc(&w->h, n));
-        IMM_TRY(dalloc(&w->inv_off, n + 1));
         IMM_TRY(dalloc(&w->scan_tmp, scan_tmp_elems(n)));
         IMM_TRY(dalloc(&w->cursor, n));
         IMM_TRY(dalloc(&w->n_covered, 1));
         HIP_TRY(hipHostMalloc((void**)&w->host_cov, sizeof(unsigned long long), hipHostMallocDefault));
-    }
-    const int64_t members = (int64_t)p->sum.placed;
-    if (members > w->cap_inv) {
-        dfree(w->inv);
-        int64_t c = members + members / 4 + 1024;
-        IMM_TRY(dalloc(&w->inv, c));
-        w->cap_inv = c;
     }
     if (count > w->cap_cov) {
         dfree(w->covered);
@@ -539,17 +540,63 @@ static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t
     return IMM_OK;
 }
 
+// Indexes sets [set_lo, set_lo + set_n) with counts cnt (n entries) as segment w->nseg,
+// entries holding rel0 + (set - set_lo); members is an upper bound on their total.
+static imm_status index_segment(imm_pool* p, SelectWs* w, const uint32_t* cnt, int64_t set_lo,
+                                int64_t set_n, uint32_t rel0, int64_t members, hipStream_t s) {
+    const int64_t n = p->g->n;
+    SelectWs::IndexSeg& x = w->seg[w->nseg];
+    if (!x.off) IMM_TRY(dalloc(&x.off, n + 1));
+    if (members > x.cap) {
+        dfree(x.inv);
+        const int64_t c = members + members / 4 + 1024;
+        IMM_TRY(dalloc(&x.inv, c));
+        x.cap = c;
+    }
+    HIP_TRY(launch_scan_u32(cnt, n, x.off, w->scan_tmp, s));
+    HIP_TRY(launch_fill_u32(w->cursor, n, 0u, s));
+    HIP_TRY(launch_inv_scatter(p->rr_start, p->rr_len, p->ids, set_lo, set_n, rel0, x.off, w->cursor,
+                               x.inv, s));
+    ++w->nseg;
+    return IMM_OK;
+}
+
 imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t k,
-                               hipStream_t s, SelInst* out) {
+                               hipStream_t s, SelInst* out, bool segments) {
     const int32_t n = p->g->n;
     IMM_TRY(ensure_select(p, w, count, k));
     const uint32_t* hsrc = nullptr;
     IMM_TRY(range_hist(p, w, first, count, &hsrc, s));
     HIP_TRY(launch_copy_hist(hsrc, w->h, n, s));
-    HIP_TRY(launch_scan_u32(hsrc, n, w->inv_off, w->scan_tmp, s));
-    HIP_TRY(launch_fill_u32(w->cursor, n, 0u, s));
-    HIP_TRY(launch_inv_scatter(p->rr_start, p->rr_len, p->ids, first, count, w->inv_off, w->cursor,
-                               w->inv, s));
+    const bool prefix = first == 0 && count == p->count;      // hsrc is the pool histogram
+    const int64_t placed = (int64_t)p->sum.placed;
+    if (segments && prefix && w->ix_pool == p && w->snap_valid && w->ix_first == 0 &&
+        w->nseg > 0 && w->ix_end <= count && (w->ix_end == count || w->nseg < kMaxSegs)) {
+        if (w->ix_end < count) {
+            // a longer prefix of the same pool: index only the sets drawn since
+            if (!w->hist_tmp) IMM_TRY(dalloc(&w->hist_tmp, n));
+            HIP_TRY(launch_sub_u32(p->hist, w->snap, w->hist_tmp, n, s));
+            IMM_TRY(index_segment(p, w, w->hist_tmp, w->ix_end, count - w->ix_end,
+                                  (uint32_t)w->ix_end, placed - w->ix_members, s));
+            HIP_TRY(hipMemcpyAsync(w->snap, p->hist, sizeof(uint32_t) * (size_t)n,
+                                   hipMemcpyDeviceToDevice, s));
+            w->ix_end = count;
+            w->ix_members = placed;
+        }
+    } else {
+        w->nseg = 0;
+        IMM_TRY(index_segment(p, w, hsrc, first, count, 0u, placed, s));
+        w->ix_pool = p;
+        w->ix_first = first;
+        w->ix_end = first + count;
+        w->snap_valid = segments && prefix;
+        if (w->snap_valid) {
+            if (!w->snap) IMM_TRY(dalloc(&w->snap, n));
+            HIP_TRY(hipMemcpyAsync(w->snap, p->hist, sizeof(uint32_t) * (size_t)n,
+                                   hipMemcpyDeviceToDevice, s));
+            w->ix_members = placed;
+        }
+    }
     HIP_TRY(launch_fill_u32(w->covered, count, 0u, s));
     HIP_TRY(launch_fill_u64(w->keys, k, 0ull, s));
     HIP_TRY(launch_fill_u64(w->n_covered, 1, 0ull, s));
@@ -560,8 +607,13 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
     si.first = first;
     si.count = count;
     si.h = w->h;
-    si.inv_off = w->inv_off;
-    si.inv = w->inv;
+    si.inv_off = w->seg[0].off;
+    si.inv = w->seg[0].inv;
+    si.nseg = w->nseg;
+    for (int32_t j = 0; j < w->nseg; ++j) {
+        si.seg_off[j] = w->seg[j].off;
+        si.seg_inv[j] = w->seg[j].inv;
+    }
     si.rr_start = p->rr_start;
     si.rr_len = p->rr_len;
     si.ids = p->ids;
@@ -611,7 +663,7 @@ static imm_status pool_select(imm_pool* p, int64_t first, int64_t count, int32_t
                               int32_t* seeds_out, int64_t* covered_out, hipStream_t s,
                               int64_t need = 0) {
     SelInst si;
-    IMM_TRY(select_prepare(p, &p->sel, first, count, k, s, &si));
+    IMM_TRY(select_prepare(p, &p->sel, first, count, k, s, &si, true));
     si.need = need;
     SelectWs* w = &p->sel;
     IMM_TRY(select_run(&p->launch, &w, &si, 1, s));

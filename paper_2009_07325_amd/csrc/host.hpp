@@ -170,14 +170,27 @@ namespace imm {
 // Selection workspace: one per concurrent selection (a pool has one; a server has one per
 // active query).
 struct SelectWs {
+    // One segment of the inverted index: the sets of one range, vertex-major.
+    struct IndexSeg {
+        int64_t* off = nullptr;               // n + 1
+        uint32_t* inv = nullptr;              // relative set indices
+        int64_t cap = 0;
+    };
     int64_t n = 0;
     int32_t* h = nullptr;
     uint32_t* hist_tmp = nullptr;
-    int64_t* inv_off = nullptr;
     int64_t* scan_tmp = nullptr;
     uint32_t* cursor = nullptr;
-    int64_t cap_inv = 0;
-    uint32_t* inv = nullptr;
+    // The index covers sets [ix_first, ix_end) of pool ix_pool in nseg segments.  When the
+    // next selection reads a longer prefix of the same pool, only the new sets are indexed
+    // (their counts are the pool histogram minus snap, the histogram at ix_end).
+    IndexSeg seg[kMaxSegs];
+    int32_t nseg = 0;
+    const imm_pool* ix_pool = nullptr;
+    int64_t ix_first = 0, ix_end = 0;
+    int64_t ix_members = 0;                   // pool members in [0, ix_end) (prefix index)
+    uint32_t* snap = nullptr;
+    bool snap_valid = false;
     int64_t cap_cov = 0;
     uint32_t* covered = nullptr;
     int64_t cap_k = 0;
@@ -284,8 +297,9 @@ imm_status check_range(const imm_pool* p, int64_t first, int64_t count);
 
 // Launches the per-selection setup kernels (counts, inverted index, clears) on `s` and
 // fills `out` with the instance descriptor.
+// segments: the index may be kept as segments across calls (single-instance launches only)
 imm_status select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t k,
-                          hipStream_t s, SelInst* out);
+                          hipStream_t s, SelInst* out, bool segments = false);
 // Runs all rounds of every prepared instance in one cooperative launch, then copies each
 // instance's seeds and covered count to its workspace's pinned buffers (synchronises s).
 imm_status select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,

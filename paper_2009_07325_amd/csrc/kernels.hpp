@@ -123,12 +123,17 @@ hipError_t launch_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* 
                            hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, const int32_t* ids,
-                              int64_t first, int64_t count, const int64_t* inv_off,
+                              int64_t first, int64_t count, uint32_t rel0, const int64_t* inv_off,
                               uint32_t* cursor, uint32_t* inv, hipStream_t s);
+// out[v] = a[v] - b[v]
+hipError_t launch_sub_u32(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStream_t s);
 // All k rounds of greedy selection for one or more instances in one cooperative launch:
 // per round a segmented argmax over every instance's counters, a grid barrier, the cover
 // step of every instance, a grid barrier.
+// Inverted-index segments one selection may read (sets of successive estimation phases).
+constexpr int kMaxSegs = 16;
+
 struct SelInst {
     int32_t n;
     int32_t k;
@@ -149,6 +154,13 @@ struct SelInst {
     // below it the phase fails whatever the remaining seeds are, and the instance stops.
     // 0: always run all k rounds.
     int64_t need;
+    // A single-instance launch may read its index as segments: the entries of v are those
+    // of every segment j, seg_inv[j][seg_off[j][v] .. seg_off[j][v + 1]).  nseg == 1 means
+    // inv_off / inv alone (the only form multi-instance launches accept).
+    int32_t nseg;
+    int32_t pad0;
+    const int64_t* seg_off[kMaxSegs];
+    const uint32_t* seg_inv[kMaxSegs];
 };
 // Arrival counters of a hierarchical grid barrier (zeroed before each launch): block b
 // arrives on sub[b % 16]; the last arrival of a group bumps top; all wait for top.

@@ -166,10 +166,11 @@ hipError_t launch_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* 
 }
 
 // ---- inverted index: vertex -> relative RR indices (one wave per set) ---------------
+// Entries hold rel0 + the set's index within [first, first + count).
 __global__ void k_inv_scatter(const int64_t* __restrict__ rr_start, const int32_t* __restrict__ rr_len,
                               const int32_t* __restrict__ ids, int64_t first, int64_t count,
-                              const int64_t* __restrict__ inv_off, uint32_t* __restrict__ cursor,
-                              uint32_t* __restrict__ inv) {
+                              uint32_t rel0, const int64_t* __restrict__ inv_off,
+                              uint32_t* __restrict__ cursor, uint32_t* __restrict__ inv) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -179,19 +180,34 @@ __global__ void k_inv_scatter(const int64_t* __restrict__ rr_start, const int32_
         for (int32_t j = lane; j < len; j += kWave) {
             const int32_t v = ids[s + j];
             const uint32_t at = atomic_add_agent(cursor + v, 1u);
-            inv[inv_off[v] + at] = (uint32_t)i;
+            inv[inv_off[v] + at] = rel0 + (uint32_t)i;
         }
     }
 }
 
 hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, const int32_t* ids,
-                              int64_t first, int64_t count, const int64_t* inv_off,
+                              int64_t first, int64_t count, uint32_t rel0, const int64_t* inv_off,
                               uint32_t* cursor, uint32_t* inv, hipStream_t s) {
     if (count == 0) return hipSuccess;
     int64_t blocks = (count * kWave + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    k_inv_scatter<<<(unsigned)blocks, 256, 0, s>>>(rr_start, rr_len, ids, first, count, inv_off,
-                                                   cursor, inv);
+    k_inv_scatter<<<(unsigned)blocks, 256, 0, s>>>(rr_start, rr_len, ids, first, count, rel0,
+                                                   inv_off, cursor, inv);
+    return hipGetLastError();
+}
+
+__global__ void k_sub_u32(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                          uint32_t* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i] - b[i];
+}
+
+hipError_t launch_sub_u32(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_sub_u32<<<(unsigned)blocks, 256, 0, s>>>(a, b, out, n);
     return hipGetLastError();
 }
 
@@ -356,6 +372,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     __shared__ CoverLds cov_all[kCoopWaves];
     __shared__ DecCache dc;
     __shared__ unsigned char stopped[kMaxInst];   // estimation phase decided (failed)
+    __shared__ int64_t seg_pre[kMaxSegs + 1];     // single instance: its entries per segment
+    __shared__ int64_t seg_beg[kMaxSegs];
     for (int i = threadIdx.x; i < kDecSlots; i += blockDim.x) {
         dc.key[i] = kDecEmpty;
         dc.cnt[i] = 0;
@@ -428,9 +446,22 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             } else {
                 live = true;
                 const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
-                const int64_t beg = global(I.inv_off)[u];
-                ent_beg[tid] = beg;
-                cnt = global(I.inv_off)[u + 1] - beg;
+                if (I.nseg > 1) {              // only in single-instance launches
+                    int64_t acc = 0;
+                    for (int j = 0; j < I.nseg; ++j) {
+                        const int64_t b = global(I.seg_off[j])[u];
+                        seg_beg[j] = b;
+                        seg_pre[j] = acc;
+                        acc += global(I.seg_off[j])[u + 1] - b;
+                    }
+                    seg_pre[I.nseg] = acc;
+                    ent_beg[tid] = 0;
+                    cnt = acc;
+                } else {
+                    const int64_t beg = global(I.inv_off)[u];
+                    ent_beg[tid] = beg;
+                    cnt = global(I.inv_off)[u + 1] - beg;
+                }
                 if (blockIdx.x == 0) st_co(global(I.seeds) + round, u);
             }
         }
@@ -463,7 +494,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 }
                 li = lo;
                 const SelInst& I = inst[lo];
-                const uint32_t rel = global(I.inv)[ent_beg[lo] + (e - ent_pre[lo])];
+                uint32_t rel;
+                if (I.nseg > 1) {
+                    const int64_t q = e - ent_pre[lo];
+                    int j = 0;
+                    while (j + 1 < I.nseg && seg_pre[j + 1] <= q) ++j;
+                    rel = global(I.seg_inv[j])[seg_beg[j] + (q - seg_pre[j])];
+                } else {
+                    rel = global(I.inv)[ent_beg[lo] + (e - ent_pre[lo])];
+                }
                 fresh = ld_co(global(I.covered) + rel) == 0u;
                 if (fresh) {
                     st_co(global(I.covered) + rel, 1u);

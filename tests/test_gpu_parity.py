@@ -133,6 +133,30 @@ def test_select_matches_oracle(imm_gpu, first, count, k):
     assert len(set(seeds_g.tolist())) == k
 
 
+def test_select_growing_prefixes_match_oracle(imm_gpu):
+    """Selections over longer and longer prefixes of one pool read the inverted index as
+    segments (one per batch of new sets, more segments than a solve makes); every
+    selection must equal the oracle's greedy and a fresh pool's single-segment one."""
+    g = graphs.rmat(12, 12 << 12, seed=91)
+    ic_p = graphs.weighted_cascade(g)
+    gg = _gpu_graph(imm_gpu, g, ic_p=ic_p)
+    seed = 0x5EED0301
+    pool = imm_gpu.Pool.create(gg, imm_gpu.IMM_IC, seed)
+    ref = oracle.Pool(g, oracle.IC, seed, ic_p=ic_p)
+    ends = [500, 700, 1000, 1600, 2600, 4000] + [4000 + 300 * i for i in range(1, 14)]
+    for end in ends:
+        imm_gpu.imm_generate_rr(pool.handle, end)
+        seeds_g, cov_g = imm_gpu.imm_select_seeds(pool.handle, 0, end, 15)
+        ref.extend(end)
+        seeds_o, cov_o = ref.greedy(15, 0, end)
+        assert np.array_equal(seeds_g, seeds_o), end
+        assert cov_g == cov_o, end
+    fresh = imm_gpu.Pool.create(gg, imm_gpu.IMM_IC, seed)
+    imm_gpu.imm_generate_rr(fresh.handle, ends[-1])
+    seeds_f, cov_f = imm_gpu.imm_select_seeds(fresh.handle, 0, ends[-1], 15)
+    assert np.array_equal(seeds_f, seeds_g) and cov_f == cov_g
+
+
 def _solve_both(imm, g, model, k, eps, ell, seed, ic_p=None, lt_w=None, fresh=False):
     gg = _gpu_graph(imm, g, ic_p=ic_p, lt_w=lt_w, lt=(model == imm.IMM_LT))
     seeds_g, info = imm.imm_solve(gg.handle, k, eps, ell, model, seed, fresh_final=fresh)
