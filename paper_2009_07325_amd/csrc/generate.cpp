@@ -45,7 +45,8 @@ imm_status GenCtx::init(int device_, imm_model model_, int cus_, const GenTuning
 
 int64_t GenCtx::bytes() const {
     return (int64_t)grid * 4 * vis_words * 4 + hslots * (vis_words * 4 + vis_n * 4) +
-           cap_queue * 8 + cap_inst * (int64_t)(sizeof(GenInst) + 8 + sizeof(PoolSummary));
+           cap_queue * (handoff ? 12 : 8) + (arena ? kArenaWords * 4 : 0) +
+           cap_inst * (int64_t)(sizeof(GenInst) + 8 + sizeof(PoolSummary));
 }
 
 void GenCtx::release() {
@@ -55,6 +56,8 @@ void GenCtx::release() {
     dfree(lc);
     hfree(host_lc);
     dfree(queue);
+    dfree(handoff);
+    dfree(arena);
     dfree(d_inst);
     hfree(host_inst);
     dfree(d_work_off);
@@ -134,10 +137,13 @@ imm_status ensure_inst(GenCtx* c, int64_t ninst, int64_t queue) {
     }
     if (queue > c->cap_queue) {
         dfree(c->queue);
+        dfree(c->handoff);
         c->cap_queue = 0;
         IMM_TRY(dalloc(&c->queue, queue));
+        if (c->model == IMM_IC) IMM_TRY(dalloc(&c->handoff, queue));
         c->cap_queue = queue;
     }
+    if (c->model == IMM_IC && !c->arena) IMM_TRY(dalloc(&c->arena, kArenaWords));
     return IMM_OK;
 }
 
@@ -259,6 +265,9 @@ imm_status imm::gen_run(GenCtx* c, imm_pool* const* pools, const int64_t* upto, 
         L.budget = c->budget;
         L.lc = c->lc;
         L.heavy_list = c->queue;
+        L.handoff = c->handoff;
+        L.arena = c->arena;
+        L.arena_cap = c->arena ? kArenaWords : 0;
         L.visited = c->visited;
         L.vis_words = c->vis_words;
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(c->grid, (off + 3) / 4));

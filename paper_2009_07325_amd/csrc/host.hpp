@@ -236,6 +236,8 @@ struct GenCtx {
     LaunchCounters* host_lc = nullptr;  // pinned
     int64_t cap_queue = 0;
     unsigned long long* queue = nullptr;  // light -> heavy queue
+    uint32_t* handoff = nullptr;          // per queue entry (IC)
+    int32_t* arena = nullptr;             // handed-off traversals (IC), kArenaWords
     int64_t cap_inst = 0;
     GenInst* d_inst = nullptr;
     GenInst* host_inst = nullptr;       // pinned

@@ -24,7 +24,8 @@ struct alignas(64) LaunchCounters {
     unsigned long long work;       // light work-queue cursor
     unsigned int hwork;            // heavy work-queue cursor
     unsigned int n_heavy;          // sets the light launch queued for the heavy launch
-    unsigned int pad[12];
+    unsigned long long arena;      // handoff arena words in use
+    unsigned int pad[10];
 };
 
 // Host-bound summary of one pool's counters, written by launch_pool_summary.
@@ -82,6 +83,13 @@ struct GenLaunch {
     int64_t budget;          // 4-edge groups a light wave may examine for one set
     LaunchCounters* lc;
     unsigned long long* heavy_list;  // light -> heavy queue: instance << 32 | RR index
+    // Per queue entry, the arena offset of the partial traversal the light kernel hands
+    // over (IC sets abandoned at the budget: words size, head, in-edges examined (lo, hi),
+    // then the members, of which [0, head) are expanded), or kNoHandoff: restart.  The
+    // heavy kernel adds those in-edges to the light counters when it places the set.
+    uint32_t* handoff;
+    int32_t* arena;
+    int64_t arena_cap;
     uint32_t n_queue;        // IC heavy launch: entries of heavy_list to process
     // LT walk over HBM lists: when set, the work items are heavy_in[0, total) (entries as
     // in heavy_list) instead of the instances' RR ranges
@@ -94,6 +102,8 @@ struct GenLaunch {
     int64_t list_stride;
 };
 
+constexpr uint32_t kNoHandoff = 0xFFFFFFFFu;
+constexpr int64_t kArenaWords = (int64_t)16 << 20;   // handoff arena: 64 MiB of int32
 hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s);   // 256-thread blocks
 // block: threads per heavy set, 64, 128, 256 or 1024
 hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s);

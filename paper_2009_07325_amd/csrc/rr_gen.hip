@@ -63,7 +63,10 @@ struct WaveState {
     unsigned long long chunk_base = 0;
     unsigned long long placed = 0, edges = 0;
     unsigned long long heavy_buf = 0;        // lane i holds the i-th queued (instance, r)
+    uint32_t heavy_ho = kNoHandoff;          // ... and its handoff offset
     int32_t heavy_n = 0;
+    unsigned long long ar_base = 0;          // reserved handoff arena words
+    int32_t ar_left = 0;
 };
 
 // Find the instance of work item w: largest i with work_off[i] <= w.
@@ -124,13 +127,54 @@ __device__ __forceinline__ void flush_heavy(const GenLaunch& L, WaveState& ws) {
     unsigned int at = 0;
     if (lane_id() == 0) at = atomic_add_agent(&L.lc->n_heavy, (unsigned int)ws.heavy_n);
     at = uniform(at);
-    if (lane_id() < ws.heavy_n) L.heavy_list[at + lane_id()] = ws.heavy_buf;
+    if (lane_id() < ws.heavy_n) {
+        L.heavy_list[at + lane_id()] = ws.heavy_buf;
+        if (L.handoff) L.handoff[at + lane_id()] = ws.heavy_ho;
+    }
     ws.heavy_n = 0;
 }
 
-__device__ __forceinline__ void push_heavy(const GenLaunch& L, WaveState& ws, int32_t inst, uint32_t r) {
-    if (lane_id() == ws.heavy_n) ws.heavy_buf = ((unsigned long long)(uint32_t)inst << 32) | r;
+__device__ __forceinline__ void push_heavy(const GenLaunch& L, WaveState& ws, int32_t inst, uint32_t r,
+                                           uint32_t ho = kNoHandoff) {
+    if (lane_id() == ws.heavy_n) {
+        ws.heavy_buf = ((unsigned long long)(uint32_t)inst << 32) | r;
+        ws.heavy_ho = ho;
+    }
     if (++ws.heavy_n == kWave) flush_heavy(L, ws);
+}
+
+// Copies a light set's partial traversal (members list[0, size), of which [0, head) are
+// expanded, and the in-edges examined for them) to the handoff arena; wave-cooperative.  Arena space is
+// reserved per wave in chunks of kArenaChunk words.  kNoHandoff when the arena is full.
+constexpr int32_t kArenaChunk = 4096;
+__device__ uint32_t hand_off(const GenLaunch& L, WaveState& ws, const int32_t* list, int32_t size,
+                             int32_t head, unsigned long long examined) {
+    if (!L.arena) return kNoHandoff;
+    const int32_t need = size + 4;
+    if (ws.ar_left < need) {
+        const int32_t want = max(kArenaChunk, need);
+        unsigned long long b = 0;
+        if (lane_id() == 0) b = atomic_add_agent(&L.lc->arena, (unsigned long long)want);
+        b = uniform64(b);
+        if ((int64_t)(b + (unsigned long long)want) > L.arena_cap) {
+            ws.ar_left = 0;
+            return kNoHandoff;
+        }
+        ws.ar_base = b;
+        ws.ar_left = want;
+    }
+    const unsigned long long o = ws.ar_base;
+    ws.ar_base += (unsigned long long)need;
+    ws.ar_left -= need;
+    int32_t* p = L.arena + o;
+    if (lane_id() == 0) {
+        p[0] = size;
+        p[1] = head;
+        p[2] = (int32_t)(uint32_t)examined;
+        p[3] = (int32_t)(uint32_t)(examined >> 32);
+    }
+    for (int32_t i = lane_id(); i < size; i += kWave) p[4 + i] = list[i];
+    return (uint32_t)o;
 }
 
 __device__ __forceinline__ void push_capacity_miss(const GenInst& I, uint32_t r) {
@@ -427,7 +471,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         int32_t size = 1, head = 0;
         uint64_t examined = 0;
         int64_t used = 0;
-        bool abandon = false;
+        bool abandon = false, resumable = false;
         wave_sync();
 
         while (head < size && !abandon) {
@@ -453,13 +497,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             if (lane == nb - 1) L.f.pre[nb] = incl;
             const int32_t total_small = __shfl(incl, nb - 1, kWave);
             const int64_t total = (int64_t)wave_sum((uint64_t)ng);
-            examined += wave_sum((uint64_t)dg);
+            const uint64_t level_edges = wave_sum((uint64_t)dg);
             wave_sync();
             if (used + total > G.budget) {
-                abandon = true;
+                abandon = true;                   // members [0, head) are expanded
+                resumable = true;
                 break;
             }
             used += total;
+            examined += level_edges;
 
             int32_t nst = 0;
             auto flush = [&]() { flush_light(a, L.stage, nst, list, size, abandon, vis); };
@@ -512,7 +558,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             wave_sync();
             head += nb;
         }
-        if (abandon) push_heavy(G, ws, inst, r);
+        if (abandon) {
+            // a set abandoned at the budget is handed over as it stands, with the in-edges
+            // examined so far; the heavy kernel counts them for this launch when it places
+            // the set (a set that misses the id buffer is drawn again and counts nothing)
+            push_heavy(G, ws, inst, r, resumable ? hand_off(G, ws, list, size, head, examined)
+                                                 : kNoHandoff);
+        }
         else place_wave(G, ws, slot, inst, r, list, size, examined);
         for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
         vis_fence();
@@ -564,6 +616,8 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
     __shared__ int32_t s_size;
     __shared__ uint32_t s_nchunks;
     __shared__ unsigned int s_idx;
+    __shared__ int32_t s_head;
+    __shared__ unsigned long long s_light;      // in-edges the light kernel examined
     __shared__ unsigned long long s_base;
     const int tid = threadIdx.x, lane = lane_id();
     const int wid = uniform(tid / kWave);
@@ -581,15 +635,34 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
         const GenInst& I = G.inst[(int32_t)(qe >> 32)];
         const GraphView a = ic_view(I);
         const uint32_t r = (uint32_t)qe;
-        if (tid == 0) {
+        const uint32_t ho = G.handoff ? uniform(G.handoff[idx]) : kNoHandoff;
+        if (ho != kNoHandoff) {
+            // resume the light kernel's traversal: its members, of which [0, head) are
+            // expanded, enter the list, the bitmap and (the unexpanded ones) the ring
+            const int32_t* hp = G.arena + ho;
+            const int32_t hsize = uniform(hp[0]), hhead = uniform(hp[1]);
+            for (int32_t i = tid; i < hsize; i += kHeavyBlock) {
+                const int32_t v = hp[4 + i];
+                list[i] = v;
+                vis_test_and_set(vis, v);
+                if (i >= hhead && hsize - hhead <= kRing) ring_put(ring, i, load_vrec(a.vrec + v));
+            }
+            if (tid == 0) {
+                s_size = hsize;
+                s_head = hhead;
+                s_light = ((unsigned long long)(uint32_t)hp[3] << 32) | (uint32_t)hp[2];
+            }
+        } else if (tid == 0) {
             const int32_t root = (int32_t)root_of(r, (uint32_t)a.n, a.k0, a.k1);
             list[0] = root;
             ring_put(ring, 0, load_vrec(a.vrec + root));
             vis_test_and_set(vis, root);
             s_size = 1;
+            s_head = 0;
+            s_light = 0;
         }
         __syncthreads();
-        int32_t head = 0, size = s_size;
+        int32_t head = s_head, size = s_size;
         unsigned long long examined = 0;
         while (head < size) {
             const int32_t nb = min(size - head, kHeavyBlock);
@@ -741,6 +814,7 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
                 global(I.rr_len)[r] = size;
                 atomic_add_agent(&c->placed[slot & 63], (unsigned long long)size);
                 atomic_add_agent(&c->hedges[slot & 63], (unsigned long long)examined);
+                if (s_light) atomic_add_agent(&c->edges[slot & 63], s_light);
             }
             s_base = b;
         }
