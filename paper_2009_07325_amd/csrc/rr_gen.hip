@@ -316,7 +316,7 @@ __device__ __forceinline__ void masks_of_bits(uint32_t bits, uint64_t m[4]) {
 // Live edges are staged in LDS (edge indices, per wave) and resolved in batches: the
 // source loads and visited test-and-sets of a whole batch are issued together, so the
 // group tests themselves never wait on memory.
-constexpr int kStage = 128;
+constexpr int kStage = 256;
 
 // Appends the live edges of one pass (ballot m[j] of word j of group g per lane) to the
 // wave's stage, calling flush() first whenever they would not fit.
@@ -382,7 +382,7 @@ __device__ __forceinline__ void flush_light(const GraphView& a, uint32_t* stage,
 // modulo kRing: filled when a member is found, read when its batch starts, so a batch does
 // not wait for its vertices' list entries and records.  Valid for positions [head, size)
 // while size - head <= kRing (no later member has reused the slot yet).
-constexpr int kRing = 512;
+constexpr int kRing = 256;
 struct RecRing {
     uint32_t start[kRing];
     uint32_t deg[kRing];
