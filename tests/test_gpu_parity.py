@@ -83,6 +83,25 @@ def test_rr_sets_ic_per_edge_thresholds(imm_gpu):
     _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 99, 20_000, ic_p=p)
 
 
+@pytest.mark.parametrize("budget", ["2", "16"])
+def test_rr_sets_ic_handoff(imm_gpu, monkeypatch, budget):
+    """A light budget of a few 4-edge groups: almost every set with more than one level is
+    abandoned by the light kernel at a level boundary and resumed by the heavy kernel
+    from there (handoff).  Sets, histogram and in-edges examined must equal the oracle's,
+    in chunked launches and with per-edge thresholds."""
+    monkeypatch.setenv("IMM_LIGHT_BUDGET", budget)
+    g = graphs.rmat(13, 12 << 13, seed=43)
+    _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 0x5EED0401, 6000, ic_p=graphs.weighted_cascade(g),
+                  chunks=[100, 2500, 6000])
+    p = graphs.trivalency(g, seed=44)
+    p[::5] = np.float32(0.5)
+    _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 0x5EED0402, 8000, ic_p=p)
+    w = configs.c1()
+    _, info, _ = _solve_both(imm_gpu, w.graph, imm_gpu.IMM_IC, w.k, w.eps, w.ell, w.seed,
+                             ic_p=w.ic_p)
+    assert info["rr_heavy_launches"] > 0 and info["edges_heavy"] > 0
+
+
 def test_rr_sets_ic_big_sets(imm_gpu):
     """p = 1 everywhere on a dense ER graph: RR(r) = all ancestors of the root, thousands
     of vertices, beyond the on-chip member list, so the HBM big-set path runs."""
