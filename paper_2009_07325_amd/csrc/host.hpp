@@ -256,6 +256,7 @@ struct GenCtx {
     // Defaults, then `tuning` (if given and set), then the IMM_LIGHT_BUDGET /
     // IMM_HEAVY_BLOCK / IMM_HEAVY_SCRATCH_GIB environment overrides.
     imm_status init(int device_, imm_model model_, int cus_, const GenTuning* tuning = nullptr);
+    imm_status ready();
     int64_t bytes() const;
     void release();
 };
