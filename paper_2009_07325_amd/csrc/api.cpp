@@ -520,7 +520,7 @@ static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t
         IMM_TRY(dalloc(&w->scan_tmp, scan_tmp_elems(n)));
         IMM_TRY(dalloc(&w->cursor, n));
         IMM_TRY(dalloc(&w->n_covered, 1));
-        HIP_TRY(hipHostMalloc((void**)&w->host_cov, sizeof(unsigned long long), hipHostMallocDefault));
+        IMM_TRY(halloc(&w->host_cov, 1));
     }
     if (count > w->cap_cov) {
         dfree(w->covered);
@@ -534,7 +534,7 @@ static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t
         hfree(w->host_seeds);
         IMM_TRY(dalloc(&w->keys, k));
         IMM_TRY(dalloc(&w->seeds, k));
-        HIP_TRY(hipHostMalloc((void**)&w->host_seeds, sizeof(int32_t) * (size_t)k, hipHostMallocDefault));
+        IMM_TRY(halloc(&w->host_seeds, k));
         w->cap_k = k;
     }
     return IMM_OK;
@@ -631,7 +631,7 @@ imm_status imm::select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* 
         L->release();
         IMM_TRY(dalloc(&L->d_inst, ninst));
         IMM_TRY(dalloc(&L->bar, 1));
-        HIP_TRY(hipHostMalloc((void**)&L->host_bar, sizeof(GridBarrier), hipHostMallocDefault));
+        IMM_TRY(halloc(&L->host_bar, 1));
         L->cap = ninst;
     }
     HIP_TRY(hipMemcpyAsync(L->d_inst, inst, sizeof(SelInst) * (size_t)ninst, hipMemcpyHostToDevice, s));

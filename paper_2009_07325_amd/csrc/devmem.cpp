@@ -18,6 +18,7 @@
 #include <list>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "host.hpp"
 
@@ -133,6 +134,76 @@ void dev_free(void* p) {
     }
 }
 
+// Pinned host buffers of up to 1 MiB are kept in power-of-two classes (256 B and up) once
+// freed, and handed out again; larger ones are allocated and freed directly.  Like device
+// blocks, a buffer is freed only after the copies into it have completed.
+namespace {
+
+constexpr int kHostMinClass = 8, kHostMaxClass = 20;
+
+struct HostCache {
+    std::mutex mu;
+    std::unordered_map<void*, int> live;     // handed out: class, or -1 (not cached)
+    std::vector<void*> free[kHostMaxClass + 1];
+};
+
+HostCache& host_cache() {
+    static HostCache* c = new HostCache();   // never destroyed, like the device cache
+    return *c;
+}
+
+void drop_host_free(HostCache& c) {
+    for (std::vector<void*>& v : c.free) {
+        for (void* p : v) (void)hipHostFree(p);
+        v.clear();
+    }
+}
+
+}  // namespace
+
+hipError_t host_alloc(void** out, size_t bytes) {
+    *out = nullptr;
+    int cls = kHostMinClass;
+    while (cls <= kHostMaxClass && ((size_t)1 << cls) < bytes) ++cls;
+    HostCache& c = host_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (cls <= kHostMaxClass && !c.free[cls].empty()) {
+        *out = c.free[cls].back();
+        c.free[cls].pop_back();
+        c.live[*out] = cls;
+        return hipSuccess;
+    }
+    const size_t size = cls <= kHostMaxClass ? (size_t)1 << cls : bytes;
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, size, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        drop_host_free(c);
+        e = hipHostMalloc(&p, size, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+    }
+    c.live[p] = cls <= kHostMaxClass ? cls : -1;
+    *out = p;
+    return hipSuccess;
+}
+
+void host_free(void* p) {
+    if (!p) return;
+    HostCache& c = host_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    const int cls = it == c.live.end() ? -1 : it->second;
+    if (it != c.live.end()) c.live.erase(it);
+    if (cls < 0 || !cache_enabled()) {
+        (void)hipHostFree(p);
+        return;
+    }
+    c.free[cls].push_back(p);
+}
+
 size_t dev_cached_bytes() {
     Cache& c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
@@ -147,5 +218,8 @@ extern "C" imm_status imm_release_cached_memory(void) {
     Cache& c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
     drop_free(c, -1);
+    imm::HostCache& h = imm::host_cache();
+    std::lock_guard<std::mutex> hk(h.mu);
+    imm::drop_host_free(h);
     return IMM_OK;
 }

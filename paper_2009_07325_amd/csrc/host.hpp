@@ -57,9 +57,27 @@ void dfree(T*& p) {
     p = nullptr;
 }
 
+// Small pinned host buffers (read-back of counters, coverage and seeds, launch tables) go
+// through a cache of their own: hipHostMalloc / hipHostFree cost tens of microseconds each.
+hipError_t host_alloc(void** out, size_t bytes);
+void host_free(void* p);
+
+template <typename T>
+imm_status halloc(T** p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = host_alloc(&q, sizeof(T) * (size_t)count);
+    if (e != hipSuccess)
+        return fail(IMM_ENOMEM, "pinned host allocation of %lld bytes failed: %s",
+                    (long long)(sizeof(T) * count), hipGetErrorString(e));
+    *p = static_cast<T*>(q);
+    return IMM_OK;
+}
+
 template <typename T>
 void hfree(T*& p) {
-    if (p) (void)hipHostFree(p);
+    host_free((void*)p);
     p = nullptr;
 }
 
