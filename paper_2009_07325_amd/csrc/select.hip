@@ -361,6 +361,21 @@ __device__ __forceinline__ void block_excl_scan_i64(int64_t v, int64_t* out, int
     __syncthreads();
 }
 
+// Block-wide maximum of every thread's key, merged into *key with one atomic (no-op when
+// the maximum is 0).  Called by all threads of the block.
+__device__ __forceinline__ void block_key_max(unsigned long long best,
+                                              IMM_GLOBAL unsigned long long* key,
+                                              unsigned long long* red, int lane, int wid, int tid) {
+    best = wave_max_u64(best);
+    if (lane == 0) red[wid] = best;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kCoopWaves; ++w) best = red[w] > best ? red[w] : best;
+        if (best) __hip_atomic_fetch_max(key, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __restrict__ inst,
                                                             int32_t ninst, int32_t maxk,
                                                             GridBarrier* bar) {
@@ -391,6 +406,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         // thread i keeps instance i's
         const int64_t cov_before = tid < ninst ? (int64_t)ld_co(global(inst[tid].n_covered)) : 0;
         // ---- argmax: tiles of kArgTile counters, any instance still selecting ----
+        // A block's successive tiles of one instance share one block reduction and one
+        // atomic (tiles are grouped by instance, so an instance's tiles are consecutive).
+        unsigned long long best = 0;
+        int cur = -1;                                    // instance of `best`, block-uniform
         for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
             int lo = 0, hi = ninst;                      // tile_pre[lo] <= t < tile_pre[hi]
             while (hi - lo > 1) {
@@ -399,10 +418,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             }
             const SelInst& I = inst[lo];
             if (round >= I.k || stopped[lo]) continue;   // uniform across the block
+            if (lo != cur) {
+                if (cur >= 0) block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
+                cur = lo;
+                best = 0;
+            }
             const int32_t prev = round > 0 ? ld_co(global(I.seeds) + round - 1) : -1;
             IMM_GLOBAL int32_t* h = global(I.h);
             const int64_t base = (t - tile_pre[lo]) * kArgTile;
-            unsigned long long best = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t v = base + j * kCoopBlock + tid;
@@ -419,17 +442,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                     }
                 }
             }
-            best = wave_max_u64(best);
-            if (lane == 0) red[wid] = best;
-            __syncthreads();
-            if (tid == 0) {
-                for (int w = 1; w < kCoopWaves; ++w) best = red[w] > best ? red[w] : best;
-                if (best)
-                    __hip_atomic_fetch_max(global(I.keys) + round, best, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-            }
-            __syncthreads();
         }
+        if (cur >= 0) block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
         if (!grid_sync(bar, epoch)) return;
         // ---- cover: sets containing each instance's new seed ----
         // Every block reads the same final keys and coverage, so every block takes the same
