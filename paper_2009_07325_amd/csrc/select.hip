@@ -425,23 +425,32 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             }
             const int32_t prev = round > 0 ? ld_co(global(I.seeds) + round - 1) : -1;
             IMM_GLOBAL int32_t* h = global(I.h);
+            // the block's next tile joins this one when it is of the same instance, so the
+            // counters of both are loaded together
+            const int64_t t2 = t + gridDim.x;
+            const bool pair = t2 < tile_pre[lo + 1];
             const int64_t base = (t - tile_pre[lo]) * kArgTile;
+            const int64_t base2 = (t2 - tile_pre[lo]) * kArgTile;
+            int32_t c[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t v = base + j * kCoopBlock + tid;
-                if (v < I.n) {
-                    int32_t c = ld_co(h + v);
-                    if ((int32_t)v == prev) {
-                        st_co(h + v, -1);
-                        c = -1;
-                    }
-                    if (c >= 0) {
-                        const unsigned long long key = ((unsigned long long)(uint32_t)(c + 1) << 32) |
-                                                       (unsigned long long)(0xFFFFFFFFu - (uint32_t)v);
-                        best = key > best ? key : best;
-                    }
+            for (int j = 0; j < 8; ++j) {
+                const int64_t v = (j < 4 ? base : base2) + (j & 3) * kCoopBlock + tid;
+                c[j] = (j < 4 || pair) && v < I.n ? ld_co(h + v) : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t v = (j < 4 ? base : base2) + (j & 3) * kCoopBlock + tid;
+                if (c[j] >= 0 && (int32_t)v == prev) {
+                    st_co(h + v, -1);
+                    c[j] = -1;
+                }
+                if (c[j] >= 0) {
+                    const unsigned long long key = ((unsigned long long)(uint32_t)(c[j] + 1) << 32) |
+                                                   (unsigned long long)(0xFFFFFFFFu - (uint32_t)v);
+                    best = key > best ? key : best;
                 }
             }
+            if (pair) t = t2;
         }
         if (cur >= 0) block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
         if (!grid_sync(bar, epoch)) return;
