@@ -233,6 +233,7 @@ hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStre
 constexpr int kCoopBlock = 1024;
 constexpr int kCoopWaves = kCoopBlock / kWave;
 constexpr int kArgTile = kCoopBlock * 4;       // counters per argmax tile
+constexpr int kArgGroup = 4;                     // tiles of a block loaded together
 constexpr int kMaxInst = kCoopBlock;             // instances per launch (LDS tables)
 
 template <typename T>
@@ -425,21 +426,21 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             }
             const int32_t prev = round > 0 ? ld_co(global(I.seeds) + round - 1) : -1;
             IMM_GLOBAL int32_t* h = global(I.h);
-            // the block's next tile joins this one when it is of the same instance, so the
-            // counters of both are loaded together
-            const int64_t t2 = t + gridDim.x;
-            const bool pair = t2 < tile_pre[lo + 1];
+            // up to kArgGroup of the block's successive tiles of this instance are loaded
+            // together
+            const int64_t left = (tile_pre[lo + 1] - t + gridDim.x - 1) / gridDim.x;
+            const int m = left < kArgGroup ? (int)left : kArgGroup;
             const int64_t base = (t - tile_pre[lo]) * kArgTile;
-            const int64_t base2 = (t2 - tile_pre[lo]) * kArgTile;
-            int32_t c[8];
+            const int64_t step = (int64_t)gridDim.x * kArgTile;
+            int32_t c[4 * kArgGroup];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t v = (j < 4 ? base : base2) + (j & 3) * kCoopBlock + tid;
-                c[j] = (j < 4 || pair) && v < I.n ? ld_co(h + v) : -1;
+            for (int j = 0; j < 4 * kArgGroup; ++j) {
+                const int64_t v = base + (j >> 2) * step + (j & 3) * kCoopBlock + tid;
+                c[j] = (j >> 2) < m && v < I.n ? ld_co(h + v) : -1;
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t v = (j < 4 ? base : base2) + (j & 3) * kCoopBlock + tid;
+            for (int j = 0; j < 4 * kArgGroup; ++j) {
+                const int64_t v = base + (j >> 2) * step + (j & 3) * kCoopBlock + tid;
                 if (c[j] >= 0 && (int32_t)v == prev) {
                     st_co(h + v, -1);
                     c[j] = -1;
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                     best = key > best ? key : best;
                 }
             }
-            if (pair) t = t2;
+            t += (int64_t)(m - 1) * gridDim.x;
         }
         if (cur >= 0) block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
         if (!grid_sync(bar, epoch)) return;
