@@ -98,8 +98,9 @@ imm_status imm_init(int32_t device);
 const char* imm_last_error(void);
 
 /* Device memory that objects release is kept by the library for reuse (at most 64 GiB per
- * device; it is also given back automatically when an allocation fails).  This returns all
- * of it to the HIP runtime.  Thread-safe. */
+ * device; it is also given back automatically when an allocation fails), and so are small
+ * pinned host buffers (up to 1 MiB each: read-back of counters, coverage and seeds).  This
+ * returns all of both to the HIP runtime.  Thread-safe. */
 imm_status imm_release_cached_memory(void);
 
 /* Upload a directed graph G = (V, E), gIM Sec. II-A, as the CSR of its transpose
