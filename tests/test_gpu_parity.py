@@ -219,3 +219,16 @@ def test_solve_pool_prefix_reuse(imm_gpu):
         s_alone, i_alone = imm_gpu.imm_solve(gg.handle, k, eps, 1.0, imm_gpu.IMM_IC, w.seed)
         assert np.array_equal(s_pool, s_alone)
         assert i_pool["theta"] == i_alone["theta"] and i_pool["covered"] == i_alone["covered"]
+
+
+def test_solve_after_cache_release_matches(imm_gpu):
+    """Releasing the cached device blocks and pinned host buffers between solves changes
+    nothing: the next solve allocates afresh and returns the same seeds and coverage."""
+    w = configs.c1()
+    gg = _gpu_graph(imm_gpu, w.graph, ic_p=w.ic_p)
+    s1, i1 = imm_gpu.imm_solve(gg.handle, w.k, w.eps, w.ell, imm_gpu.IMM_IC, w.seed)
+    imm_gpu.imm_release_cached_memory()
+    s2, i2 = imm_gpu.imm_solve(gg.handle, w.k, w.eps, w.ell, imm_gpu.IMM_IC, w.seed)
+    imm_gpu.imm_release_cached_memory()
+    assert np.array_equal(s1, s2)
+    assert i1["theta"] == i2["theta"] and i1["covered"] == i2["covered"]
