@@ -638,7 +638,7 @@ imm_status imm::select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* 
     // one cooperative launch per group of at most select_max_inst() instances; the barrier
     // counters start from zero for each launch, and its error flag is collected at the end
     const int32_t per = select_max_inst();
-    HIP_TRY(hipMemsetAsync(L->bar, 0, sizeof(GridBarrier), s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(L->bar), sizeof(GridBarrier) / 4, 0u, s));
     for (int32_t a = 0; a < ninst; a += per) {
         const int32_t cnt = std::min(per, ninst - a);
         int32_t maxk = 0;

@@ -638,14 +638,19 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
         const uint32_t ho = G.handoff ? uniform(G.handoff[idx]) : kNoHandoff;
         if (ho != kNoHandoff) {
             // resume the light kernel's traversal: its members, of which [0, head) are
-            // expanded, enter the list, the bitmap and (the unexpanded ones) the ring
+            // expanded, enter the list and the bitmap.  The ring receives the records of
+            // the last kRing unexpanded members, positions [max(head, size - kRing),
+            // size): whenever a later batch reads the ring (size' - head' <= kRing with
+            // size' >= size), every position it reads at or past size - kRing holds its
+            // own record, and positions past size are filled as members are found.
             const int32_t* hp = G.arena + ho;
             const int32_t hsize = uniform(hp[0]), hhead = uniform(hp[1]);
+            const int32_t ring_from = max(hhead, hsize - kRing);
             for (int32_t i = tid; i < hsize; i += kHeavyBlock) {
                 const int32_t v = hp[4 + i];
                 list[i] = v;
                 vis_test_and_set(vis, v);
-                if (i >= hhead && hsize - hhead <= kRing) ring_put(ring, i, load_vrec(a.vrec + v));
+                if (i >= ring_from) ring_put(ring, i, load_vrec(a.vrec + v));
             }
             if (tid == 0) {
                 s_size = hsize;

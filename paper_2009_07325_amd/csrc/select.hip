@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T* __restrict__
 template <typename T>
 static hipError_t scan(const T* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s) {
     if (n == 0) {
-        return hipMemsetAsync(out, 0, sizeof(int64_t), s);
+        return fill(reinterpret_cast<unsigned long long*>(out), 1, 0ull, s);
     }
     const int64_t tiles = (n + kScanTile - 1) / kScanTile;
     k_scan_tiles<T><<<(unsigned)tiles, kScanBlock, 0, s>>>(in, n, tmp);
@@ -583,10 +583,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     }
 }
 
-// One 1024-thread block per CU (16 of the CU's wave slots).  Grids sized at the occupancy
-// limit reported for this kernel (2 blocks per CU) were accepted by the cooperative launch
-// yet not all resident at once for some register allocations, which left the grid barrier
-// waiting; one block per CU keeps a wide margin.
+// One 1024-thread block per CU.  With this kernel's resources (about 92 KB of LDS and
+// 126 VGPRs per lane, i.e. 4 waves per SIMD) one block per CU is also the most a CU can
+// hold, so the grid is exactly the device's capacity and every block is resident while
+// no other kernel occupies the CUs.
 int select_coop_grid() {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
@@ -596,10 +596,21 @@ int select_coop_grid() {
 
 int select_max_inst() { return kMaxInst; }
 
-// IMM_SELECT_LAUNCH=plain launches the same grid with an ordinary launch.  The grid is
-// sized to be co-resident on an idle device, so the result is the same; the switch exists
-// for tools that do not handle cooperative launches (some profilers).  If blocks were ever
-// not co-resident, the barrier's bounded wait reports an error instead of hanging.
+// Blocks of k_select_coop that the device can hold at once: its occupancy per CU times
+// the CU count (0 if the runtime cannot tell).
+static int select_coop_capacity() {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_select_coop, kCoopBlock, 0) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+// IMM_SELECT_LAUNCH=plain launches the same grid with an ordinary launch, for tools that
+// do not handle cooperative launches (some profilers).  Either way a grid larger than the
+// device can hold at once is refused before anything is launched: its blocks could not
+// all reach the grid barrier.
 static bool plain_launch() {
     static const bool plain = [] {
         const char* e = getenv("IMM_SELECT_LAUNCH");
@@ -611,13 +622,16 @@ static bool plain_launch() {
 hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
                               hipStream_t s) {
     if (ninst < 1 || ninst > kMaxInst) return hipErrorInvalidValue;
+    const int grid = select_coop_grid();
+    const int capacity = select_coop_capacity();
+    if (capacity < 1 || grid > capacity) return hipErrorCooperativeLaunchTooLarge;
     if (plain_launch()) {
-        k_select_coop<<<select_coop_grid(), kCoopBlock, 0, s>>>(inst, ninst, maxk, bar);
+        k_select_coop<<<grid, kCoopBlock, 0, s>>>(inst, ninst, maxk, bar);
         return hipGetLastError();
     }
     void* args[] = {(void*)&inst, (void*)&ninst, (void*)&maxk, (void*)&bar};
-    return hipLaunchCooperativeKernel((const void*)k_select_coop, dim3(select_coop_grid()),
-                                      dim3(kCoopBlock), args, 0, s);
+    return hipLaunchCooperativeKernel((const void*)k_select_coop, dim3(grid), dim3(kCoopBlock), args,
+                                      0, s);
 }
 
 }  // namespace imm

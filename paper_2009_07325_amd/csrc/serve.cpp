@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -113,6 +114,26 @@ int64_t query_bytes(const imm_server* S, const Query& q, bool minimal) {
     return n * 20 + (int64_t)(members * 4.0) + (int64_t)(sets * 4.0);
 }
 
+// Device bytes that one query's next step needs on its own: the pool grown to the sets the
+// step reads (offsets, lengths and members at the pool's measured mean size; the member
+// buffer grows by doubling, so up to twice that) plus the step's selection workspace.  A
+// query whose step needs more than the whole budget can never run and is rejected with
+// IMM_ECAPACITY before its pool grows (gIM Alg. 2 / Alg. 1 sample sizes grow without
+// bound as eps shrinks, while device memory does not).
+double step_bytes(const imm_server* S, const Query& q) {
+    const double n = (double)S->g->n;
+    const double mean = S->mean_members[q.model].load();
+    const double sets = (double)q.gen_upto;
+    const double pool = sets * 12.0 + 2.0 * sets * mean * 4.0;
+    const double sel = (double)q.sel_count;
+    const double ws = n * 20.0 + sel * mean * 4.0 + sel * 4.0;
+    return pool + ws;
+}
+
+// Sets generated first on an empty pool, to measure its mean set size before any query's
+// demand is checked against the budget.
+constexpr int64_t kPilotSets = 1024;
+
 void finish(imm_server* S, Query& q, imm_status st, const std::string& err) {
     S->n_active.fetch_sub(1);
     Result r;
@@ -187,7 +208,20 @@ bool tick(imm_server* S) {
         ++i;
     }
     if (act.empty()) return true;
-    // 2. one generation per pool, to the largest demand
+    // 2. one generation per pool, to the largest demand.  An empty pool first gets a pilot
+    //    of kPilotSets sets (the same sets any query reads first) so that the mean set size
+    //    is measured; then queries whose step cannot fit the budget are rejected, and the
+    //    pool is extended for the rest.
+    auto fail_model = [&](int m, imm_status st, const std::string& err) {
+        for (size_t i = 0; i < act.size();) {
+            if (act[i].model != m) {
+                ++i;
+                continue;
+            }
+            finish(S, act[i], st, err);
+            act.erase(act.begin() + (long)i);
+        }
+    };
     for (int m = 0; m < 2; ++m) {
         imm_pool* p = S->pools[m];
         if (!p) continue;
@@ -195,47 +229,78 @@ bool tick(imm_server* S) {
         for (const Query& q : act)
             if (q.model == m) target = std::max(target, q.gen_upto);
         if (target <= p->count) continue;
-        const double t0 = now_s();
-        imm_status st = pool_generate(p, target, S->stream);
-        const double dt = now_s() - t0;
-        if (st == IMM_OK && p->count > 0)
+        double t_pilot = 0.0;
+        if (p->count < kPilotSets) {
+            const double t0 = now_s();
+            imm_status st = pool_generate(p, std::min(target, kPilotSets), S->stream);
+            t_pilot = now_s() - t0;
+            if (st != IMM_OK) {
+                fail_model(m, st, imm_last_error());
+                continue;
+            }
             S->mean_members[m].store((double)p->sum.placed / (double)p->count);
-        S->pool_sets[m].store(p->count);
+            S->pool_sets[m].store(p->count);
+        }
+        target = 0;
         for (size_t i = 0; i < act.size();) {
             Query& q = act[i];
             if (q.model != m) {
                 ++i;
                 continue;
             }
-            q.t_gen += dt;
-            if (st != IMM_OK) {
-                finish(S, q, st, imm_last_error());
+            q.t_gen += t_pilot;
+            const double need = step_bytes(S, q);
+            if (need > (double)S->budget) {
+                char msg[160];
+                snprintf(msg, sizeof msg,
+                         "query needs about %.3g bytes of device memory for %lld RR sets, more than "
+                         "the server budget of %lld",
+                         need, (long long)q.gen_upto, (long long)S->budget);
+                finish(S, q, IMM_ECAPACITY, msg);
                 act.erase(act.begin() + (long)i);
                 continue;
             }
+            target = std::max(target, q.gen_upto);
             ++i;
         }
+        if (target <= p->count) continue;
+        const double t0 = now_s();
+        imm_status st = pool_generate(p, target, S->stream);
+        const double dt = now_s() - t0;
+        if (st == IMM_OK && p->count > 0)
+            S->mean_members[m].store((double)p->sum.placed / (double)p->count);
+        S->pool_sets[m].store(p->count);
+        for (Query& q : act)
+            if (q.model == m) q.t_gen += dt;
+        if (st != IMM_OK) fail_model(m, st, imm_last_error());
     }
-    if (act.empty()) return true;
     // 3. all selections in one cooperative launch
     //    (a query whose final selection repeats its last one keeps that one's result)
     const double t0 = now_s();
     std::vector<SelInst> inst;
     std::vector<SelectWs*> ws;
-    for (size_t i = 0; i < act.size(); ++i) {
+    for (size_t i = 0; i < act.size();) {
         Query& q = act[i];
-        if (q.plan.reuses_last()) continue;
-        ws.push_back(&S->slots[q.slot]);
-        inst.emplace_back();
-        imm_status st = select_prepare(S->pools[q.model], ws.back(), q.sel_first, q.sel_count, q.k,
-                                       S->stream, &inst.back());
-        inst.back().need = q.plan.need_cov();
-        if (st != IMM_OK) {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->worker_status = st;
-            S->worker_error = imm_last_error();
-            return false;
+        if (q.plan.reuses_last()) {
+            ++i;
+            continue;
         }
+        SelInst si{};
+        imm_status st = select_prepare(S->pools[q.model], &S->slots[q.slot], q.sel_first, q.sel_count,
+                                       q.k, S->stream, &si);
+        if (st != IMM_OK) {
+            // this query's workspace did not fit: it alone fails, and its slot's memory is
+            // given back for the others
+            const std::string err = imm_last_error();
+            S->slots[q.slot].release();
+            finish(S, q, st, err);
+            act.erase(act.begin() + (long)i);
+            continue;
+        }
+        si.need = q.plan.need_cov();
+        ws.push_back(&S->slots[q.slot]);
+        inst.push_back(si);
+        ++i;
     }
     imm_status st = inst.empty() ? IMM_OK
                                  : select_run(&S->launch, ws.data(), inst.data(), (int32_t)inst.size(),

@@ -102,6 +102,52 @@ def test_rr_sets_ic_handoff(imm_gpu, monkeypatch, budget):
     assert info["rr_heavy_launches"] > 0 and info["edges_heavy"] > 0
 
 
+def _wide_handoff_graph():
+    """Hub 0 has 300 in-neighbours 1..300; each of those has in-edges from 301 and 302;
+    every other vertex (and 301, 302) has an in-edge from the hub.  A root outside 1..302
+    reaches the hub at level 1 and its 300 in-neighbours at level 2, so a light budget of
+    100 4-edge groups abandons the set with 300 unexpanded members (more than the heavy
+    kernel's 256-entry record ring), whose expansion finds only two new members."""
+    n, hub, wide = 1000, 0, 300
+    src, dst = [], []
+    for u in range(1, wide + 1):
+        src.append(u); dst.append(hub)
+        src.extend([wide + 1, wide + 2]); dst.extend([u, u])
+    for v in range(wide + 1, n):
+        src.append(hub); dst.append(v)
+    return graphs.from_edges(n, src, dst)
+
+
+@pytest.mark.parametrize("block", ["64", "256"])
+def test_rr_sets_ic_handoff_wide_level(imm_gpu, monkeypatch, block):
+    """Handoff of a set whose unexpanded members outnumber the heavy kernel's record ring:
+    every member the heavy kernel expands must use its own vertex record.  Single pools
+    (all edges live; every edge live with probability 0.97) and a batch of two instances
+    must equal the oracle."""
+    imm = imm_gpu
+    monkeypatch.setenv("IMM_LIGHT_BUDGET", "100")
+    monkeypatch.setenv("IMM_HEAVY_BLOCK", block)
+    g = _wide_handoff_graph()
+    p1 = np.ones(g.m, dtype=np.float32)
+    p2 = np.full(g.m, 0.97, dtype=np.float32)
+    for p, seed in ((p1, 0x5EED0501), (p2, 0x5EED0502)):
+        pool, ref = _compare_pool(imm, g, imm.IMM_IC, seed, 3000, ic_p=p, chunks=[700, 3000])
+        off, _ = ref.export()
+        assert (np.diff(off) > 256).sum() > 1000
+    gg1 = _gpu_graph(imm, g, ic_p=p1)
+    gg2 = _gpu_graph(imm, g, ic_p=p2)
+    items = [dict(graph=gg1, k=5, eps=0.5, ell=1.0, model=imm.IMM_IC, seed=0x5EED0503),
+             dict(graph=gg2, k=3, eps=0.4, ell=1.0, model=imm.IMM_IC, seed=0x5EED0504)]
+    stats = {}
+    res = imm.imm_batch_solve(items, stats=stats)
+    assert stats["rr_heavy_launches"] > 0
+    for (seeds, info), it, p in zip(res, items, (p1, p2)):
+        ref = oracle.imm_solve(g, oracle.IC, it["k"], it["eps"], 1.0, it["seed"], ic_p=p)
+        assert np.array_equal(seeds, ref["seeds"])
+        assert info["theta"] == ref["theta"] and info["covered"] == ref["covered"]
+        assert info["num_rr"] == ref["num_rr"] and info["lb"] == ref["lb"]
+
+
 def test_rr_sets_ic_big_sets(imm_gpu):
     """p = 1 everywhere on a dense ER graph: RR(r) = all ancestors of the root, thousands
     of vertices, beyond the on-chip member list, so the HBM big-set path runs."""

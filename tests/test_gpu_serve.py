@@ -95,3 +95,33 @@ def test_server_rejects_queries_beyond_budget(imm_gpu, served_graph):
             imm.imm_server_submit(srv, 0, 0.1, 1.0, imm.IMM_IC)   # k out of range
     finally:
         imm.imm_server_destroy(srv)
+
+
+def test_server_rejects_query_whose_pool_would_outgrow_budget(imm_gpu):
+    """Every edge live on a dense random graph: each RR set is the giant component (about
+    5000 members).  Under a 256 MiB budget, k = 2 with eps = 0.5 needs a few hundred sets
+    and is served; eps = 0.05 needs ~10^4 sets in its first estimation phase alone, so it is
+    rejected with IMM_ECAPACITY once the pool's mean set size is known, before the pool
+    grows.  The server keeps serving: later queries complete and equal solo solves."""
+    imm = imm_gpu
+    g = graphs.erdos_renyi(5000, 50_000, seed=8)
+    p = np.ones(g.m, dtype=np.float32)
+    gg = imm.Graph.from_arrays(g.n, g.in_off, g.in_src, ic_p=p)
+    srv = imm.imm_server_create(gg.handle, SEED_IC, SEED_LT, 256 << 20, 4)
+    try:
+        t_small = imm.imm_server_submit(srv, 2, 0.5, 1.0, imm.IMM_IC)
+        t_big = imm.imm_server_submit(srv, 2, 0.05, 1.0, imm.IMM_IC)
+        small = imm.imm_server_wait(srv, t_small, 2, timeout_s=60)
+        with pytest.raises(imm.ImmError) as e:
+            imm.imm_server_wait(srv, t_big, 2, timeout_s=60)
+        assert e.value.status == 3      # IMM_ECAPACITY
+        t_after = imm.imm_server_submit(srv, 3, 0.5, 1.0, imm.IMM_IC)
+        after = imm.imm_server_wait(srv, t_after, 3, timeout_s=60)
+        stats = imm.imm_server_stats_get(srv)
+    finally:
+        imm.imm_server_destroy(srv)
+    assert stats["rejected"] == 1 and stats["completed"] == 2
+    for (seeds, info), k in ((small, 2), (after, 3)):
+        s_alone, i_alone = imm.imm_solve(gg.handle, k, 0.5, 1.0, imm.IMM_IC, SEED_IC)
+        assert np.array_equal(seeds, s_alone)
+        assert info["theta"] == i_alone["theta"] and info["covered"] == i_alone["covered"]

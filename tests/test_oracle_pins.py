@@ -499,6 +499,63 @@ def test_imm_driver_phase_structure_c1():
     assert ref["phases"] == phases + 1
 
 
+def _fresh_final_case(g, ic_p, k, eps, ell, seed):
+    """gIM Alg. 2 then Alg. 1 with a fresh final sample, re-derived from mpmath sample sizes
+    and the pinned pool / greedy: returns the expected (seeds, covered, theta, num_rr,
+    phases, lb, spread_est) and the result greedy would give on the reuse reading."""
+    n = g.n
+    _, lam1, lam2 = _mp_quantities(n, k, eps, ell)
+    pool = oracle.Pool(g, oracle.IC, seed, ic_p=ic_p)
+    ep = math.sqrt(2) * eps
+    lb, used, phases = 1.0, 0, 0
+    for i in range(1, int(mpmath.floor(mpmath.log(n, 2))) - 1 + 1):
+        x = n / 2 ** i
+        used = max(used, int(mpmath.ceil(lam1 / x)))
+        pool.extend(used)
+        _, cov = pool.greedy(k, 0, used)
+        phases += 1
+        if n * cov / used >= (1 + ep) * x:
+            lb = n * cov / used / (1 + ep)
+            break
+    theta = int(mpmath.ceil(lam2 / lb))
+    # the final sample: fresh indices [|R_est|, |R_est| + theta), selected on their own
+    pool.extend(used + theta)
+    off, ids = pool.export(used, theta)
+    seeds, cov = oracle.greedy_sets(n, off, ids, k)
+    off0, ids0 = pool.export(0, used + theta)
+    reuse = oracle.greedy_sets(n, off0, ids0, k)
+    return dict(seeds=seeds, covered=cov, theta=theta, num_rr=used + theta, phases=phases + 1,
+                lb=lb, spread_est=n * cov / theta), reuse
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny"])
+def test_imm_driver_fresh_final_sample(case):
+    """fresh_final = 1 (the corrected IMM of Chen, CSoNet'18; reading of gIM Alg. 1): the
+    final theta sets are indices [|R_est|, |R_est| + theta), disjoint from the estimation
+    sets, and greedy runs on exactly those.  The driver's seeds, covered count, set count
+    and estimate must equal the re-derivation; the reuse reading ([0, upto)) must not."""
+    if case == "c1":
+        w = configs.c1()
+        g, p, k, eps, ell, seed = w.graph, w.ic_p, w.k, w.eps, w.ell, w.seed
+    else:
+        g = _tiny_graph()
+        p = np.array([0.3, 0.8, 0.5, 0.25, 0.6, 0.9, 0.4, 0.7, 0.2, 0.55, 0.35], dtype=np.float32)
+        k, eps, ell, seed = 2, 0.3, 1.0, 0x5EED00F1
+    exp, reuse = _fresh_final_case(g, p, k, eps, ell, seed)
+    got = oracle.imm_solve(g, oracle.IC, k, eps, ell, seed, ic_p=p, fresh_final=True)
+    assert got["seeds"].tolist() == exp["seeds"].tolist()
+    assert got["covered"] == exp["covered"]
+    assert got["theta"] == exp["theta"]
+    assert got["num_rr"] == exp["num_rr"]
+    assert got["phases"] == exp["phases"]
+    assert abs(got["lb"] / exp["lb"] - 1) < 1e-12
+    assert got["spread_est"] == exp["spread_est"]
+    # the test tells the readings apart: the reuse range gives another answer
+    assert (reuse[0].tolist(), reuse[1]) != (exp["seeds"].tolist(), exp["covered"])
+    plain = oracle.imm_solve(g, oracle.IC, k, eps, ell, seed, ic_p=p, fresh_final=False)
+    assert plain["num_rr"] == max(exp["num_rr"] - exp["theta"], exp["theta"])
+
+
 # ---- P11: end-to-end approximation guarantee on a tiny graph ----------------------------------
 def test_p11_imm_meets_guarantee_on_tiny_graph():
     g = _tiny_graph()
