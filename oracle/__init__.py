@@ -74,6 +74,18 @@ def lib():
         L.orc_imax.restype = i32
         L.orc_imm_solve.argtypes = [i32, i64, p, p, p, p, ctypes.c_int, u64, i32, dbl, dbl,
                                     ctypes.c_int, ctypes.c_int, p, p, p]
+        for f in (L.orc_rr_ic_round, L.orc_rr_lt_round):
+            f.argtypes = [i32, p, p, p, u64, u32, u32, p, p, p]
+            f.restype = i64
+        L.orc_mr_sets.argtypes = [i32, p, p, p, ctypes.c_int, u64, i32, i64, p, p, p, p]
+        L.orc_greedy_partition.argtypes = [i32, i32, i64, p, p, i32, p, p]
+        L.orc_mr_ratio.argtypes = [i32]
+        L.orc_mr_ratio.restype = dbl
+        for f in (L.orc_mr_lambda_prime, L.orc_mr_lambda_star):
+            f.argtypes = [i64, i64, i32, dbl, dbl]
+            f.restype = dbl
+        L.orc_mrim_solve.argtypes = [i32, i64, p, p, p, p, ctypes.c_int, u64, i32, i32, dbl,
+                                     dbl, p, p, p]
         _lib = L
     return _lib
 
@@ -236,6 +248,77 @@ def imm_solve(graph, model: int, k: int, eps: float, ell: float, seed: int, ic_p
                              threads or default_threads(), _ptr(seeds), _ptr(ii), _ptr(dd))
     if rc != 0:
         raise ValueError(f"oracle imm_solve failed ({rc})")
+    return dict(seeds=seeds, theta=int(ii[0]), num_rr=int(ii[1]), covered=int(ii[2]),
+                phases=int(ii[3]), edges=int(ii[4]), pool_ids=int(ii[5]), lb=float(dd[0]),
+                spread_est=float(dd[1]), lambda_prime=float(dd[2]), lambda_star=float(dd[3]))
+
+
+# ---- multi-round IM (gIM Sec. IV-H: CR-NAIMM) ----------------------------------------------
+def rr_set_round(graph, model: int, thr: np.ndarray, seed: int, r: int, t: int):
+    """Round t's RR set of multi-round set r (discovery order) and its edges examined."""
+    in_off = np.ascontiguousarray(graph.in_off, dtype=np.int64)
+    in_src = np.ascontiguousarray(graph.in_src, dtype=np.int32)
+    out = np.zeros(graph.n, dtype=np.int32)
+    mark = np.zeros(graph.n, dtype=np.uint8)
+    ex = np.zeros(1, dtype=np.int64)
+    f = lib().orc_rr_ic_round if model == IC else lib().orc_rr_lt_round
+    sz = f(graph.n, _ptr(in_off), _ptr(in_src), _ptr(thr), seed, r, t, _ptr(out), _ptr(mark),
+           _ptr(ex))
+    return out[:sz].copy(), int(ex[0])
+
+
+def mr_sets(graph, model: int, seed: int, rounds: int, count: int, ic_p=None, lt_w=None):
+    """Multi-round RR sets [0, count): offsets, elements t * n + u (sorted per set), and the
+    in-edges examined."""
+    in_off = np.ascontiguousarray(graph.in_off, dtype=np.int64)
+    in_src = np.ascontiguousarray(graph.in_src, dtype=np.int32)
+    thr = encode_ic(ic_p) if model == IC else encode_lt(in_off, lt_w)
+    off = np.zeros(count + 1, dtype=np.int64)
+    tot = np.zeros(1, dtype=np.int64)
+    ed = np.zeros(1, dtype=np.int64)
+    L = lib()
+    if L.orc_mr_sets(graph.n, _ptr(in_off), _ptr(in_src), _ptr(thr), model, seed, rounds, count,
+                     None, None, _ptr(tot), None) != 0:
+        raise ValueError("invalid multi-round set arguments")
+    ids = np.zeros(int(tot[0]), dtype=np.int32)
+    L.orc_mr_sets(graph.n, _ptr(in_off), _ptr(in_src), _ptr(thr), model, seed, rounds, count,
+                  _ptr(off), _ptr(ids), None, _ptr(ed))
+    return off, ids, int(ed[0])
+
+
+def greedy_partition(part_size: int, parts: int, off: np.ndarray, ids: np.ndarray, k: int):
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    seeds = np.zeros(parts * k, dtype=np.int32)
+    cov = np.zeros(1, dtype=np.int64)
+    if lib().orc_greedy_partition(part_size, parts, len(off) - 1, _ptr(off), _ptr(ids), k,
+                                  _ptr(seeds), _ptr(cov)) != 0:
+        raise ValueError("invalid greedy arguments")
+    return seeds, int(cov[0])
+
+
+def mr_lambda_prime(n: int, k: int, rounds: int, eps: float, ell: float) -> float:
+    return lib().orc_mr_lambda_prime(n, k, rounds, eps, ell_adjusted(n, ell))
+
+
+def mr_lambda_star(n: int, k: int, rounds: int, eps: float, ell: float) -> float:
+    return lib().orc_mr_lambda_star(n, k, rounds, eps, ell_adjusted(n, ell))
+
+
+def mrim_solve(graph, model: int, k: int, rounds: int, eps: float, ell: float, seed: int,
+               ic_p=None, lt_w=None) -> dict:
+    """CR-NAIMM: seeds are elements t * n + u (round t, vertex u) in selection order."""
+    in_off = np.ascontiguousarray(graph.in_off, dtype=np.int64)
+    in_src = np.ascontiguousarray(graph.in_src, dtype=np.int32)
+    p = None if ic_p is None else np.ascontiguousarray(ic_p, dtype=np.float32)
+    w = None if lt_w is None else np.ascontiguousarray(lt_w, dtype=np.uint32)
+    seeds = np.zeros(rounds * k, dtype=np.int32)
+    ii = np.zeros(6, dtype=np.int64)
+    dd = np.zeros(4, dtype=np.float64)
+    rc = lib().orc_mrim_solve(graph.n, len(in_src), _ptr(in_off), _ptr(in_src), _ptr(p), _ptr(w),
+                              model, seed, k, rounds, eps, ell, _ptr(seeds), _ptr(ii), _ptr(dd))
+    if rc != 0:
+        raise ValueError(f"oracle mrim_solve failed ({rc})")
     return dict(seeds=seeds, theta=int(ii[0]), num_rr=int(ii[1]), covered=int(ii[2]),
                 phases=int(ii[3]), edges=int(ii[4]), pool_ids=int(ii[5]), lb=float(dd[0]),
                 spread_est=float(dd[1]), lambda_prime=float(dd[2]), lambda_star=float(dd[3]))

@@ -111,6 +111,15 @@ int32_t orc_root(uint64_t seed, uint32_t r, int32_t n) {
 int64_t orc_rr_ic(int32_t n, const int64_t* in_off, const int32_t* in_src,
                   const uint32_t* thr, uint64_t seed, uint32_t r, int32_t* out,
                   uint8_t* mark, int64_t* edges) {
+    return orc_rr_ic_round(n, in_off, in_src, thr, seed, r, 0u, out, mark, edges);
+}
+
+/* The same search in the live-edge instance of round t (Sec. IV-H: one search per round
+ * from the set's one root; round t's draws use counter word t, so the rounds' instances
+ * are independent and round 0 is the plain one). */
+int64_t orc_rr_ic_round(int32_t n, const int64_t* in_off, const int32_t* in_src,
+                        const uint32_t* thr, uint64_t seed, uint32_t r, uint32_t t,
+                        int32_t* out, uint8_t* mark, int64_t* edges) {
     int64_t size = 0, head = 0, examined = 0;
     int32_t root = orc_root(seed, r, n);
     out[size++] = root;
@@ -119,7 +128,7 @@ int64_t orc_rr_ic(int32_t n, const int64_t* in_off, const int32_t* in_src,
         int32_t u = out[head++];
         for (int64_t e = in_off[u]; e < in_off[u + 1]; ++e) {
             ++examined;
-            uint32_t x = draw_word(seed, r, (uint32_t)(e >> 2), 0u, ORC_DOMAIN_IC, (int)(e & 3));
+            uint32_t x = draw_word(seed, r, (uint32_t)(e >> 2), t, ORC_DOMAIN_IC, (int)(e & 3));
             int live = (thr[e] == ORC_ALWAYS) || (x < thr[e]);
             int32_t w = in_src[e];
             if (live && !mark[w]) {
@@ -140,6 +149,12 @@ int64_t orc_rr_ic(int32_t n, const int64_t* in_off, const int32_t* in_src,
 int64_t orc_rr_lt(int32_t n, const int64_t* in_off, const int32_t* in_src,
                   const uint32_t* cum, uint64_t seed, uint32_t r, int32_t* out,
                   uint8_t* mark, int64_t* edges) {
+    return orc_rr_lt_round(n, in_off, in_src, cum, seed, r, 0u, out, mark, edges);
+}
+
+int64_t orc_rr_lt_round(int32_t n, const int64_t* in_off, const int32_t* in_src,
+                        const uint32_t* cum, uint64_t seed, uint32_t r, uint32_t t,
+                        int32_t* out, uint8_t* mark, int64_t* edges) {
     int64_t size = 0, examined = 0;
     int32_t v = orc_root(seed, r, n);
     out[size++] = v;
@@ -148,7 +163,7 @@ int64_t orc_rr_lt(int32_t n, const int64_t* in_off, const int32_t* in_src,
         int64_t s = in_off[v], e = in_off[v + 1];
         if (e == s) break;
         examined += e - s;
-        uint32_t x = draw_word(seed, r, (uint32_t)v, 0u, ORC_DOMAIN_LT, 0);
+        uint32_t x = draw_word(seed, r, (uint32_t)v, t, ORC_DOMAIN_LT, 0);
         int64_t pick = -1;
         for (int64_t j = s; j < e; ++j) {
             if (cum[j] == ORC_ALWAYS || x < cum[j]) {
@@ -446,5 +461,212 @@ int orc_imm_solve(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in
 out:
     orc_pool_free(pool);
     free(thr);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Multi-round influence maximisation (gIM Sec. IV-H, Table 3: the CR-NAIMM algorithm of
+ * Sun et al., KDD'18).  Influence spreads in T rounds, each an independent diffusion from
+ * that round's seed set S_t (|S_t| <= k); the objective is the expected number of nodes
+ * activated in at least one round.  A random multi-round RR set draws one root and runs
+ * one reverse search per round t from it, in round t's own live-edge instance; its
+ * elements are (node, round) pairs, stored as t * n + u.  A seed collection S (elements
+ * (u, t) with at most k per round) covers the set when it shares an element with it, and
+ * n times the covered fraction estimates the objective, as Eq. 3 does for one round.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n, rounds;
+    const int64_t* in_off;
+    const int32_t* in_src;
+    const uint32_t* thr;
+    int model;
+    uint64_t seed;
+    int64_t count;
+    int64_t* off;       /* count + 1 */
+    int32_t* ids;       /* elements t * n + u, sorted per set */
+    int64_t cap_sets, cap_ids, edges;
+} orc_mr_pool;
+
+/* Sets [count, upto) of a multi-round pool: set r is the union over t of
+ * {t * n + u : u in RR_t(r)}. */
+static int mr_extend(orc_mr_pool* p, int64_t upto) {
+    if (upto <= p->count) return 0;
+    if (upto > 0xFFFFFFFFll) return -1;
+    if (upto > p->cap_sets) {
+        while (p->cap_sets < upto) p->cap_sets *= 2;
+        p->off = (int64_t*)realloc(p->off, (size_t)(p->cap_sets + 1) * sizeof(int64_t));
+    }
+    int32_t* out = (int32_t*)malloc(sizeof(int32_t) * (size_t)p->n);
+    uint8_t* mark = (uint8_t*)calloc((size_t)p->n, 1);
+    for (int64_t r = p->count; r < upto; ++r) {
+        int64_t at = p->off[r];
+        for (int32_t t = 0; t < p->rounds; ++t) {
+            int64_t ex = 0, sz;
+            if (p->model == 0)
+                sz = orc_rr_ic_round(p->n, p->in_off, p->in_src, p->thr, p->seed, (uint32_t)r,
+                                     (uint32_t)t, out, mark, &ex);
+            else
+                sz = orc_rr_lt_round(p->n, p->in_off, p->in_src, p->thr, p->seed, (uint32_t)r,
+                                     (uint32_t)t, out, mark, &ex);
+            p->edges += ex;
+            qsort(out, (size_t)sz, sizeof(int32_t), cmp_i32);
+            if (at + sz > p->cap_ids) {
+                while (p->cap_ids < at + sz) p->cap_ids *= 2;
+                p->ids = (int32_t*)realloc(p->ids, (size_t)p->cap_ids * sizeof(int32_t));
+            }
+            for (int64_t i = 0; i < sz; ++i) p->ids[at + i] = t * p->n + out[i];
+            at += sz;
+        }
+        p->off[r + 1] = at;
+        p->count = r + 1;
+    }
+    free(out);
+    free(mark);
+    return 0;
+}
+
+/* Greedy over a partition matroid (CR-Greedy of Sun et al.): the ground set is
+ * n_elem = parts * part_size elements, element e belonging to part e / part_size, and at
+ * most k elements may be taken per part.  Each of the parts * k steps takes, among the
+ * elements not yet taken whose part still has room, one contained in the most uncovered
+ * sets (the smallest element among equals), then removes the sets it covers.  With one
+ * part this is orc_greedy_sets. */
+int orc_greedy_partition(int32_t part_size, int32_t parts, int64_t nsets, const int64_t* off,
+                         const int32_t* ids, int32_t k, int32_t* seeds, int64_t* covered) {
+    if (part_size < 1 || parts < 1 || k < 1 || k > part_size) return -1;
+    const int64_t n_elem = (int64_t)part_size * parts;
+    int64_t* cnt = (int64_t*)calloc((size_t)n_elem, sizeof(int64_t));
+    uint8_t* chosen = (uint8_t*)calloc((size_t)n_elem, 1);
+    int32_t* taken = (int32_t*)calloc((size_t)parts, sizeof(int32_t));
+    uint8_t* done = (uint8_t*)calloc((size_t)(nsets > 0 ? nsets : 1), 1);
+    for (int64_t i = off[0]; i < off[nsets]; ++i) cnt[ids[i]]++;
+    int64_t ncov = 0;
+    for (int32_t step = 0; step < parts * k; ++step) {
+        int64_t best = -1;
+        for (int64_t e = 0; e < n_elem; ++e) {
+            if (chosen[e] || taken[e / part_size] >= k) continue;
+            if (best < 0 || cnt[e] > cnt[best]) best = e;
+        }
+        chosen[best] = 1;
+        taken[best / part_size]++;
+        seeds[step] = (int32_t)best;
+        for (int64_t r = 0; r < nsets; ++r) {
+            if (done[r]) continue;
+            int hit = 0;
+            for (int64_t i = off[r]; i < off[r + 1]; ++i)
+                if (ids[i] == best) { hit = 1; break; }
+            if (!hit) continue;
+            done[r] = 1;
+            ++ncov;
+            for (int64_t i = off[r]; i < off[r + 1]; ++i) cnt[ids[i]]--;
+        }
+    }
+    free(cnt); free(chosen); free(taken); free(done);
+    if (covered) *covered = ncov;
+    return 0;
+}
+
+/* Sample sizes of the multi-round problem, read from IMM's (Tang et al.) with the two
+ * quantities its proofs take from the problem: the union bound runs over the
+ * C(n,k)^T feasible seed collections (ln C(n,k) becomes T ln C(n,k)), and the greedy's
+ * approximation ratio is 1 - 1/e for one round but 1/2 for a partition matroid of T >= 2
+ * parts.  With T = 1 both are IMM's own. */
+double orc_mr_ratio(int32_t rounds) { return rounds == 1 ? 1.0 - 1.0 / ORC_E : 0.5; }
+
+double orc_mr_lambda_prime(int64_t n, int64_t k, int32_t rounds, double eps, double ell_adj) {
+    double ep = sqrt(2.0) * eps;
+    double lnC = (double)rounds * orc_log_binom(n, k);
+    volatile double l2 = log2((double)n);
+    return (2.0 + 2.0 / 3.0 * ep) * (lnC + ell_adj * ln_of((double)n) + ln_of(l2)) *
+           (double)n / (ep * ep);
+}
+
+double orc_mr_lambda_star(int64_t n, int64_t k, int32_t rounds, double eps, double ell_adj) {
+    double g = orc_mr_ratio(rounds);
+    double lnC = (double)rounds * orc_log_binom(n, k);
+    double a = sqrt(ell_adj * ln_of((double)n) + ln_of(2.0));
+    double b = sqrt(g * (lnC + ell_adj * ln_of((double)n) + ln_of(2.0)));
+    return 2.0 * (double)n * (g * a + b) * (g * a + b) / (eps * eps);
+}
+
+/* CR-NAIMM: IMM's estimation loop (gIM Alg. 2) and final sample (Alg. 1) over multi-round
+ * RR sets, with the partition-matroid greedy.  seeds: int32[rounds * k], elements
+ * t * n + u in selection order.  info_i / info_d as orc_imm_solve. */
+int orc_mrim_solve(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                   const float* ic_p, const uint32_t* lt_w, int model, uint64_t seed,
+                   int32_t k, int32_t rounds, double eps, double ell,
+                   int32_t* seeds, int64_t* info_i, double* info_d) {
+    if (n < 2 || m < 0 || k < 1 || k > n || rounds < 1 || rounds > 32 ||
+        (int64_t)n * rounds > 0x7FFFFFFFll || !(eps > 0.0 && eps < 1.0) || !(ell > 0.0))
+        return -1;
+    uint32_t* thr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(m > 0 ? m : 1));
+    int rc = (model == 0) ? (ic_p ? orc_encode_ic(m, ic_p, thr) : -1)
+                          : orc_encode_lt(n, in_off, lt_w, thr);
+    if (rc != 0) { free(thr); return -2; }
+    orc_mr_pool P = {n, rounds, in_off, in_src, thr, model, seed, 0, NULL, NULL, 1024, 1 << 16, 0};
+    P.off = (int64_t*)calloc((size_t)P.cap_sets + 1, sizeof(int64_t));
+    P.ids = (int32_t*)malloc((size_t)P.cap_ids * sizeof(int32_t));
+
+    double L = orc_ell_adjusted(n, ell);
+    double ep = sqrt(2.0) * eps;
+    double lamP = orc_mr_lambda_prime(n, k, rounds, eps, L);
+    double lamS = orc_mr_lambda_star(n, k, rounds, eps, L);
+    int32_t imax = orc_imax(n);
+    double LB = 1.0;
+    int64_t cov = 0, phases = 0;
+    for (int32_t i = 1; i <= imax; ++i) {
+        double x = (double)n / (double)((int64_t)1 << i);
+        int64_t th = (int64_t)ceil(lamP / x);
+        if (mr_extend(&P, th > P.count ? th : P.count) != 0) { rc = -3; goto out; }
+        orc_greedy_partition(n, rounds, P.count, P.off, P.ids, k, seeds, &cov);
+        ++phases;
+        if ((double)n * (double)cov / (double)P.count >= (1.0 + ep) * x) {
+            LB = (double)n * (double)cov / (double)P.count / (1.0 + ep);
+            break;
+        }
+    }
+    {
+        int64_t theta = (int64_t)ceil(lamS / LB);
+        int64_t upto = theta > P.count ? theta : P.count;
+        if (mr_extend(&P, upto) != 0) { rc = -3; goto out; }
+        orc_greedy_partition(n, rounds, upto, P.off, P.ids, k, seeds, &cov);
+        ++phases;
+        info_i[0] = theta;
+        info_i[1] = P.count;
+        info_i[2] = cov;
+        info_i[3] = phases;
+        info_i[4] = P.edges;
+        info_i[5] = P.off[P.count];
+        info_d[0] = LB;
+        info_d[1] = (double)n * (double)cov / (double)upto;
+        info_d[2] = lamP;
+        info_d[3] = lamS;
+    }
+out:
+    free(P.off);
+    free(P.ids);
+    free(thr);
+    return rc;
+}
+
+/* Multi-round RR sets [0, count) of (graph, model, seed, rounds), for tests: off[count+1]
+ * and ids (elements t * n + u, sorted per set); ids == NULL returns the member total in
+ * *total only. */
+int orc_mr_sets(int32_t n, const int64_t* in_off, const int32_t* in_src, const uint32_t* thr,
+                int model, uint64_t seed, int32_t rounds, int64_t count, int64_t* off,
+                int32_t* ids, int64_t* total, int64_t* edges) {
+    if (n < 1 || rounds < 1 || count < 0) return -1;
+    orc_mr_pool P = {n, rounds, in_off, in_src, thr, model, seed, 0, NULL, NULL, 1024, 1 << 16, 0};
+    P.off = (int64_t*)calloc((size_t)P.cap_sets + 1, sizeof(int64_t));
+    P.ids = (int32_t*)malloc((size_t)P.cap_ids * sizeof(int32_t));
+    int rc = mr_extend(&P, count);
+    if (rc == 0) {
+        if (total) *total = P.off[count];
+        if (edges) *edges = P.edges;
+        if (off) memcpy(off, P.off, sizeof(int64_t) * (size_t)(count + 1));
+        if (ids) memcpy(ids, P.ids, sizeof(int32_t) * (size_t)P.off[count]);
+    }
+    free(P.off);
+    free(P.ids);
     return rc;
 }

@@ -12,10 +12,11 @@
  *
  * Random-number contract (shared by definition, not by code, with the GPU library):
  *   key     = (seed mod 2^32, seed >> 32)
- *   counter = (r, g, t, domain), domain ROOT=1, IC=2, LT=3, t = 0
+ *   counter = (r, g, t, domain), domain ROOT=1, IC=2, LT=3, t = the round (0 for plain
+ *             IMM; 0 .. T-1 for the T rounds of a multi-round set)
  *   root of RR set r : w0 of Philox(r, 0, 0, ROOT), root = (w0 * n) >> 32
- *   IC edge e of set r: word (e & 3) of Philox(r, e >> 2, 0, IC)
- *   LT vertex v of set r: w0 of Philox(r, v, 0, LT)
+ *   IC edge e of set r: word (e & 3) of Philox(r, e >> 2, t, IC)
+ *   LT vertex v of set r: w0 of Philox(r, v, t, LT)
  *
  * Every function returns 0 on success and a negative value on invalid input.
  */
@@ -57,6 +58,15 @@ int64_t orc_rr_lt(int32_t n, const int64_t* in_off, const int32_t* in_src,
                   const uint32_t* cum, uint64_t seed, uint32_t r, int32_t* out,
                   uint8_t* mark, int64_t* edges);
 
+/* The same with the round word t of the counter (multi-round IM, gIM Sec. IV-H): the
+ * live-edge instance of round t of set r; t = 0 is the plain set. */
+int64_t orc_rr_ic_round(int32_t n, const int64_t* in_off, const int32_t* in_src,
+                        const uint32_t* thr, uint64_t seed, uint32_t r, uint32_t t,
+                        int32_t* out, uint8_t* mark, int64_t* edges);
+int64_t orc_rr_lt_round(int32_t n, const int64_t* in_off, const int32_t* in_src,
+                        const uint32_t* cum, uint64_t seed, uint32_t r, uint32_t t,
+                        int32_t* out, uint8_t* mark, int64_t* edges);
+
 /* A growable collection of RR sets with indices [0, count), each stored sorted. */
 typedef struct orc_pool orc_pool;
 orc_pool* orc_pool_new(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
@@ -89,6 +99,23 @@ int orc_imm_solve(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in
                   const float* ic_p, const uint32_t* lt_w, int model, uint64_t seed,
                   int32_t k, double eps, double ell, int fresh_final, int nthreads,
                   int32_t* seeds, int64_t* info_i, double* info_d);
+
+/* Multi-round IM (gIM Sec. IV-H; CR-NAIMM of Sun et al., KDD'18).  Elements of a
+ * multi-round RR set are (u, t) pairs stored as t * n + u. */
+int orc_mr_sets(int32_t n, const int64_t* in_off, const int32_t* in_src, const uint32_t* thr,
+                int model, uint64_t seed, int32_t rounds, int64_t count, int64_t* off,
+                int32_t* ids, int64_t* total, int64_t* edges);
+/* Greedy under a partition matroid: parts of part_size elements, at most k per part. */
+int orc_greedy_partition(int32_t part_size, int32_t parts, int64_t nsets, const int64_t* off,
+                         const int32_t* ids, int32_t k, int32_t* seeds, int64_t* covered);
+double orc_mr_ratio(int32_t rounds);
+double orc_mr_lambda_prime(int64_t n, int64_t k, int32_t rounds, double eps, double ell_adj);
+double orc_mr_lambda_star(int64_t n, int64_t k, int32_t rounds, double eps, double ell_adj);
+/* seeds: int32[rounds * k]; info_i / info_d as orc_imm_solve. */
+int orc_mrim_solve(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                   const float* ic_p, const uint32_t* lt_w, int model, uint64_t seed,
+                   int32_t k, int32_t rounds, double eps, double ell,
+                   int32_t* seeds, int64_t* info_i, double* info_d);
 
 #ifdef __cplusplus
 }
