@@ -86,6 +86,8 @@ def lib():
             f.restype = dbl
         L.orc_mrim_solve.argtypes = [i32, i64, p, p, p, p, ctypes.c_int, u64, i32, i32, dbl,
                                      dbl, p, p, p]
+        L.orc_spread_mc.argtypes = [i32, i64, p, p, p, ctypes.c_int, u64, i32, p, i32, i64,
+                                    ctypes.c_int, p, p]
         _lib = L
     return _lib
 
@@ -322,3 +324,22 @@ def mrim_solve(graph, model: int, k: int, rounds: int, eps: float, ell: float, s
     return dict(seeds=seeds, theta=int(ii[0]), num_rr=int(ii[1]), covered=int(ii[2]),
                 phases=int(ii[3]), edges=int(ii[4]), pool_ids=int(ii[5]), lb=float(dd[0]),
                 spread_est=float(dd[1]), lambda_prime=float(dd[2]), lambda_star=float(dd[3]))
+
+
+# ---- forward Monte-Carlo spread (gIM Sec. II-C) -------------------------------------------
+def spread_mc(graph, model: int, seeds, sims: int, seed: int, ic_p=None, lt_w=None,
+              rounds: int = 1, threads: int | None = None, per_sim: bool = False):
+    """Vertices reached from `seeds` (elements t * n + u when rounds > 1) summed over
+    simulations [0, sims); with per_sim also each simulation's count."""
+    in_off = np.ascontiguousarray(graph.in_off, dtype=np.int64)
+    in_src = np.ascontiguousarray(graph.in_src, dtype=np.int32)
+    thr = encode_ic(ic_p) if model == IC else encode_lt(in_off, lt_w)
+    el = np.ascontiguousarray(seeds, dtype=np.int32)
+    ps = np.zeros(max(sims, 1), dtype=np.int64) if per_sim else None
+    tot = np.zeros(1, dtype=np.int64)
+    rc = lib().orc_spread_mc(graph.n, len(in_src), _ptr(in_off), _ptr(in_src), _ptr(thr), model,
+                             seed, rounds, _ptr(el), len(el), sims, threads or default_threads(),
+                             _ptr(ps), _ptr(tot))
+    if rc != 0:
+        raise ValueError("invalid spread arguments")
+    return (int(tot[0]), ps[:sims]) if per_sim else int(tot[0])

@@ -670,3 +670,121 @@ int orc_mr_sets(int32_t n, const int64_t* in_off, const int32_t* in_src, const u
     free(P.ids);
     return rc;
 }
+
+/* ------------------------------------------------------------------------------------
+ * Forward Monte-Carlo influence spread (gIM Sec. II-C, the estimator of Kempe et al.):
+ * simulation j draws an instance graph (IC: each edge kept with its probability; LT: each
+ * vertex keeps at most one in-edge, edge e with its normalised weight) and counts the
+ * vertices reachable from the seeds in it; E[I(S)] is the mean over simulations.  For
+ * seeds of several rounds (Sec. IV-H) round t draws its own instance and the count is of
+ * the vertices reached in at least one round.
+ *
+ * Draws (a contract of their own, independent of the RR sets' draws):
+ *   IC edge e in simulation j, round t: word 0 of Philox(j, e, t, FWD_IC = 4); the edge
+ *     is kept iff the word < thr[e] or thr[e] is ORC_ALWAYS (the IC encoding above);
+ *   LT vertex v in simulation j, round t: word 0 of Philox(j, v, t, FWD_LT = 5); v keeps
+ *     the first in-edge e whose cumulative threshold cum[e] exceeds the word (or is
+ *     ORC_ALWAYS), none if there is no such edge (the LT encoding above).
+ * The reachable set is found by a plain breadth-first search over out-edges, built here
+ * from the in-edge lists.
+ * ---------------------------------------------------------------------------------- */
+#define ORC_DOMAIN_FWD_IC 4u
+#define ORC_DOMAIN_FWD_LT 5u
+
+/* LT: the in-edge vertex v keeps in instance (j, t), or -1. */
+static int64_t fwd_lt_pick(const int64_t* in_off, const uint32_t* cum, uint64_t seed, uint32_t j,
+                           uint32_t t, int32_t v) {
+    uint32_t x = draw_word(seed, j, (uint32_t)v, t, ORC_DOMAIN_FWD_LT, 0);
+    for (int64_t e = in_off[v]; e < in_off[v + 1]; ++e)
+        if (cum[e] == ORC_ALWAYS || x < cum[e]) return e;
+    return -1;
+}
+
+int orc_spread_mc(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                  const uint32_t* thr_or_cum, int model, uint64_t seed, int32_t rounds,
+                  const int32_t* elems, int32_t nelem, int64_t sims, int nthreads,
+                  int64_t* per_sim, int64_t* total) {
+    if (n < 1 || m < 0 || rounds < 1 || nelem < 0 || sims < 0 || sims > 0xFFFFFFFFll ||
+        m > 0xFFFFFFFFll || (int64_t)n * rounds > 0x7FFFFFFFll)
+        return -1;
+    for (int32_t i = 0; i < nelem; ++i)
+        if (elems[i] < 0 || (int64_t)elems[i] >= (int64_t)n * rounds) return -1;
+    /* out-edge lists: out_off by counting sources, then each in-edge (u -> v, e) placed */
+    int64_t* out_off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t* out_dst = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int64_t* out_eid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    int64_t* fill = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < m; ++e) out_off[in_src[e] + 1]++;
+    for (int32_t u = 0; u < n; ++u) out_off[u + 1] += out_off[u];
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = in_off[v]; e < in_off[v + 1]; ++e) {
+            int32_t u = in_src[e];
+            int64_t at = out_off[u] + fill[u]++;
+            out_dst[at] = v;
+            out_eid[at] = e;
+        }
+    free(fill);
+    int64_t sum = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(+ : sum)
+    {
+        uint8_t* mark = (uint8_t*)calloc((size_t)n, 1);     /* this round's search */
+        uint8_t* seen = (uint8_t*)calloc((size_t)n, 1);     /* any round of this simulation */
+        int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t* reached = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t js = 0; js < sims; ++js) {
+            const uint32_t j = (uint32_t)js;
+            int64_t count = 0;
+            for (int32_t t = 0; t < rounds; ++t) {
+                int64_t size = 0, head = 0;
+                for (int32_t i = 0; i < nelem; ++i) {
+                    if (elems[i] / n != t) continue;
+                    int32_t s = elems[i] % n;
+                    if (!mark[s]) {
+                        mark[s] = 1;
+                        queue[size++] = s;
+                    }
+                }
+                while (head < size) {
+                    int32_t u = queue[head++];
+                    for (int64_t a = out_off[u]; a < out_off[u + 1]; ++a) {
+                        int32_t v = out_dst[a];
+                        if (mark[v]) continue;
+                        int64_t e = out_eid[a];
+                        int live;
+                        if (model == 0) {
+                            uint32_t x = draw_word(seed, j, (uint32_t)e, (uint32_t)t, ORC_DOMAIN_FWD_IC, 0);
+                            live = thr_or_cum[e] == ORC_ALWAYS || x < thr_or_cum[e];
+                        } else {
+                            live = fwd_lt_pick(in_off, thr_or_cum, seed, j, (uint32_t)t, v) == e;
+                        }
+                        if (live) {
+                            mark[v] = 1;
+                            queue[size++] = v;
+                        }
+                    }
+                }
+                for (int64_t i = 0; i < size; ++i) {
+                    int32_t v = queue[i];
+                    mark[v] = 0;
+                    if (!seen[v]) {
+                        seen[v] = 1;
+                        reached[count++] = v;
+                    }
+                }
+            }
+            for (int64_t i = 0; i < count; ++i) seen[reached[i]] = 0;
+            if (per_sim) per_sim[js] = count;
+            sum += count;
+        }
+        free(mark);
+        free(seen);
+        free(queue);
+        free(reached);
+    }
+    free(out_off);
+    free(out_dst);
+    free(out_eid);
+    if (total) *total = sum;
+    return 0;
+}

@@ -117,6 +117,17 @@ int orc_mrim_solve(int32_t n, int64_t m, const int64_t* in_off, const int32_t* i
                    int32_t k, int32_t rounds, double eps, double ell,
                    int32_t* seeds, int64_t* info_i, double* info_d);
 
+/* Forward Monte-Carlo influence spread (gIM Sec. II-C): over simulations j in [0, sims),
+ * the number of vertices reached from the seed elements (t * n + u: vertex u seeds round
+ * t) in at least one round's instance graph.  IC edge e kept iff word 0 of Philox(j, e, t,
+ * 4) < thr[e] (or thr[e] saturated); LT vertex v keeps the first in-edge e with word 0 of
+ * Philox(j, v, t, 5) < cum[e] (or cum[e] saturated).  per_sim (sims entries, or NULL)
+ * receives each simulation's count, *total their sum. */
+int orc_spread_mc(int32_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                  const uint32_t* thr_or_cum, int model, uint64_t seed, int32_t rounds,
+                  const int32_t* elems, int32_t nelem, int64_t sims, int nthreads,
+                  int64_t* per_sim, int64_t* total);
+
 #ifdef __cplusplus
 }
 #endif
