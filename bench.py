@@ -2,13 +2,18 @@
 """Throughput benchmark of the IMM hot path on one MI355X.
 
 One step = one full IMM solve (gIM Alg. 2 LB estimation + Alg. 1 final sample and greedy
-max coverage) on a graph already resident in HBM: R-MAT scale 20 (2^20 vertices, 2^24
-edges), weighted-cascade IC probabilities, k = 50, eps = 0.1, ell = 1.
+max coverage) on a graph already resident in HBM.  Default workload: R-MAT scale 22 (2^22
+vertices, 2^26 edges), LT with uniform(0, 1] in-weights normalised per vertex, k = 100,
+eps = 0.1, ell = 1 (the shape of soc-LiveJournal1); `--workload c2` is R-MAT scale 20 with
+weighted-cascade IC, k = 50.
 
 Prints ONE JSON line: the metric is RR sets generated per second over the whole solve
-(value), with edges examined per second, seconds per query, the roofline of the dominant
-kernel (RR generation, bound by integer ALU work: Philox4x32-10 evaluations) measured
-from HIP events around its launches, and the CPU oracle timed on a bounded sample.
+(value), with edges examined per second, seconds per query (warm, and cold: graph upload
+and first allocations included), the roofline of the dominant generation kernel measured
+from HIP events around its launches (LT walk: bytes and walk steps per second against
+HBM; IC: Philox4x32-10 evaluations against the integer-ALU peak), the forward Monte-Carlo
+spread of the returned seeds, a check against the oracle's stored full-size results, and
+the CPU oracle timed on bounded samples (all cores and one thread).
 """
 from __future__ import annotations
 
@@ -71,6 +76,20 @@ def describe(w) -> dict:
             "pool_seed": hex(w.seed)}
 
 
+def golden_check(w, seeds, info):
+    """Compares a solve with the oracle's stored full-size result of the same workload
+    (tests/golden, written by the oracle alone); None when there is none."""
+    name = {"C2": "c2", "C3": "c3"}.get(w.name.split("-")[0])
+    path = os.path.join(ROOT, "tests", "golden", f"full_size_{name}.json") if name else None
+    if not path or not os.path.exists(path):
+        return None
+    gold = json.load(open(path))
+    return (list(map(int, seeds)) == gold["seeds"] and info["theta"] == gold["theta"] and
+            info["num_rr"] == gold["num_rr"] and info["covered"] == gold["covered"] and
+            info["edges_examined"] == gold["edges_examined"] and
+            info["lb"] == float.fromhex(gold["lb_hex"]))
+
+
 def traffic_from_profile(kernel: str, workload_name: str):
     """HBM bytes per launch from the committed counter summary, if it matches the current
     kernel source; None otherwise."""
@@ -86,12 +105,12 @@ def traffic_from_profile(kernel: str, workload_name: str):
         return None
 
 
-def cpu_baseline(w, seconds: float) -> dict:
+def cpu_baseline(w, seconds: float, threads: int | None = None) -> dict:
     """The oracle (as it stands) on a bounded sample of the same workload: RR sets
     [0, S) generated in chunks until `seconds` of generation, then greedy selection of
     k seeds over them; throughput = S / (generation + selection time)."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    threads = threads or min(os.cpu_count() or 1, 16)
     pool = oracle.Pool(w.graph, oracle.IC if w.model == "IC" else oracle.LT, w.seed,
                        ic_p=w.ic_p, lt_w=w.lt_w)
     t0 = time.perf_counter()
@@ -348,6 +367,76 @@ def bench_serve(args) -> int:
     return 0 if mismatched == 0 else 1
 
 
+# ---------------------------------------------------------------------------------------
+# Parameter sweeps (gIM Sec. IV-E Fig. 4-6: k and eps; Sec. IV-F Fig. 7: graph density)
+# ---------------------------------------------------------------------------------------
+def oracle_rate(w, seconds: float) -> float:
+    """RR sets per second of the oracle on all host cores (at most 16), bounded sample."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    pool = oracle.Pool(w.graph, oracle.IC if w.model == "IC" else oracle.LT, w.seed,
+                       ic_p=w.ic_p, lt_w=w.lt_w)
+    t0 = time.perf_counter()
+    count, chunk = 0, 1000
+    while time.perf_counter() - t0 < seconds:
+        count += chunk
+        pool.extend(count, threads=threads)
+        chunk = min(chunk * 2, 50_000)
+    return count / (time.perf_counter() - t0)
+
+
+def bench_sweep(args) -> int:
+    import numpy as np
+    import paper_2009_07325_amd as imm
+    from synth import configs, graphs
+    imm.imm_init(0)
+    plan = []          # (workload, [(k, eps)])
+    if args.sweep == "k":
+        ks = [1, 10, 25, 50, 100, 200]
+        plan = [(configs.c2(), [(k, 0.1) for k in ks]), (configs.c3(), [(k, 0.1) for k in ks])]
+    elif args.sweep == "eps":
+        plan = [(configs.c2(), [(50, e) for e in (0.05, 0.1, 0.2, 0.3, 0.4, 0.5)])]
+    else:
+        for r in (2, 4, 8, 16, 32):
+            t = time.perf_counter()
+            g = graphs.barabasi_albert(1_000_000, r, seed=0xBA00 + r)
+            log(f"BA r={r}: m={g.m} built in {time.perf_counter() - t:.1f}s")
+            w = configs.Workload(f"BA-n1e6-r{r}-wc-ic", g, "IC", graphs.weighted_cascade(g), None,
+                                 k=50, eps=0.05, ell=1.0, seed=0x5EED0BA0 + r)
+            plan.append((w, [(50, 0.05)]))
+    points = []
+    for w, qs in plan:
+        model = imm.IMM_IC if w.model == "IC" else imm.IMM_LT
+        gg = imm.Graph.from_arrays(w.graph.n, w.graph.in_off, w.graph.in_src, ic_p=w.ic_p,
+                                   lt_w=w.lt_w, lt=(w.model == "LT"))
+        cpu = oracle_rate(w, args.sweep_cpu_seconds) if args.sweep_cpu_seconds > 0 else None
+        for k, eps in qs:
+            imm.imm_solve(gg.handle, k, eps, 1.0, model, w.seed)           # warm-up
+            runs = []
+            for _ in range(args.sweep_reps):
+                seeds, info = imm.imm_solve(gg.handle, k, eps, 1.0, model, w.seed)
+                runs.append(info)
+            ts = sorted(i["t_total_s"] for i in runs)
+            med = ts[len(ts) // 2]
+            info = runs[-1]
+            pt = {"workload": w.name, "n": w.graph.n, "m": w.graph.m, "model": w.model, "k": k,
+                  "eps": eps, "s_per_query": med, "s_min": ts[0], "s_max": ts[-1],
+                  "theta": info["theta"], "num_rr": info["num_rr"], "lb": info["lb"],
+                  "phases": info["phases"], "rr_sets_s": info["num_rr"] / med,
+                  "gteps": info["edges_examined"] / med / 1e9,
+                  "t_generate_s": info["t_generate_s"], "t_select_s": info["t_select_s"],
+                  "oracle_rr_sets_s": cpu,
+                  "rate_vs_oracle": (info["num_rr"] / med / cpu) if cpu else None}
+            points.append(pt)
+            log(json.dumps(pt))
+        del gg
+    out = {"metric": METRIC, "sweep": args.sweep, "n_gpus": 1, "reps": args.sweep_reps,
+           "unit": "s/query", "higher_is_better": False, "dtype": "u32",
+           "data": "synthetic (seeded graphs; no dataset)", "points": points}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def copy_calibration(nbytes: int, reps: int) -> int:
     """Launches a plain device-to-device copy kernel of known size (torch's elementwise
     copy of nbytes) `reps` times: the reference that scales HBM byte counters read under a
@@ -373,7 +462,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--queries", type=int, default=200, help="c5: queries in the stream")
     ap.add_argument("--qps", type=float, default=20.0, help="c5: offered queries per second")
     ap.add_argument("--max-active", type=int, default=16, help="c5: queries in flight at most")
@@ -385,7 +474,16 @@ def main() -> int:
                     help="c1-c3: tune the generation launch on this many pilot sets first "
                          "(outside the timed region; results do not change)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds-1t", type=float, default=8.0,
+                    help="single-thread oracle sample (the paper's one-core IMM analogue)")
+    ap.add_argument("--spread-sims", type=int, default=1000,
+                    help="forward Monte-Carlo simulations scoring the returned seeds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", choices=["k", "eps", "density"], default=None,
+                    help="runtime sweeps: k (IC and LT, eps 0.1), eps (IC, k 50), density "
+                         "(Barabasi-Albert n 1e6, r 2..32, k 50, eps 0.05)")
+    ap.add_argument("--sweep-reps", type=int, default=3)
+    ap.add_argument("--sweep-cpu-seconds", type=float, default=3.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy kernel of BYTES (profiler counter scale)")
     args = ap.parse_args()
@@ -398,6 +496,9 @@ def main() -> int:
 
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 5)
+    if args.sweep:
+        log("host:", json.dumps(host_info()))
+        return bench_sweep(args)
     if args.workload == "c4":
         log("host:", json.dumps(host_info()))
         return bench_batch(args)
@@ -490,6 +591,27 @@ def main() -> int:
             "steps_per_s": sum(i["pool_ids"] for i in infos) / lt_time if lt_time > 0 else 0.0,
         }
     last = infos[-1]
+    golden = golden_check(w, seeds, last)
+    # solution quality: forward Monte-Carlo spread of the returned seeds (gIM Sec. II-C)
+    spread = None
+    if args.spread_sims > 0:
+        t = time.perf_counter()
+        sp = imm.imm_spread_mc(g.handle, model, seeds, args.spread_sims, 0x5EEDF00D)
+        spread = {"sims": args.spread_sims, "mean": sp["mean"], "stderr": sp["stderr"],
+                  "ris_estimate": last["spread_est"], "seconds": time.perf_counter() - t}
+        log(f"spread of the seeds: {sp['mean']:.1f} +- {sp['stderr']:.1f} over "
+            f"{args.spread_sims} simulations (RIS estimate {last['spread_est']:.1f})")
+    # cold query: graph upload (host arrays -> HBM, encoding) and first allocations included,
+    # as the paper's runtimes include allocation and transfer
+    imm.imm_release_cached_memory()
+    t = time.perf_counter()
+    g_cold = imm.Graph.from_arrays(w.graph.n, w.graph.in_off, w.graph.in_src, ic_p=w.ic_p,
+                                   lt_w=w.lt_w, lt=(w.model == "LT"))
+    t_upload = time.perf_counter() - t
+    seeds_cold, _ = imm.imm_solve(g_cold.handle, w.k, w.eps, w.ell, model, w.seed)
+    t_cold = time.perf_counter() - t
+    del g_cold
+    log(f"cold query: {t_cold * 1e3:.1f} ms (graph upload {t_upload * 1e3:.1f} ms)")
     out = {
         "metric": METRIC,
         "value": sets / elapsed,
@@ -506,6 +628,11 @@ def main() -> int:
         "config": describe(w),
         "gteps": edges / elapsed / 1e9,
         "s_per_query": elapsed / args.steps,
+        "cold_s_per_query": t_cold,
+        "graph_upload_s": t_upload,
+        "cold_equals_warm": bool((seeds_cold == seeds).all()),
+        "golden_match": golden,
+        "spread_mc": spread,
         "theta": last["theta"],
         "num_rr": last["num_rr"],
         "lb": last["lb"],
@@ -518,8 +645,11 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if args.cpu_seconds_1t > 0:
+            log("cpu baseline: oracle on one thread ...")
+            out["cpu_baseline_single_thread"] = cpu_baseline(w, args.cpu_seconds_1t, threads=1)
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if golden in (None, True) else 1
 
 
 if __name__ == "__main__":

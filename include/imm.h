@@ -22,10 +22,10 @@
  *
  * Random-number contract (what makes results reproducible bit for bit): Philox4x32-10
  * (Salmon et al., SC'11) with key (seed mod 2^32, seed >> 32) and counter
- * (r, g, 0, domain):
+ * (r, g, t, domain), t the round (0 except in multi-round sets, below):
  *    root of RR set r     : word 0 of counter (r, 0, 0, 1); root = (word * n) >> 32
- *    IC test of in-edge e : word (e & 3) of counter (r, e >> 2, 0, 2)
- *    LT draw at vertex v  : word 0 of counter (r, v, 0, 3)
+ *    IC test of in-edge e : word (e & 3) of counter (r, e >> 2, t, 2)
+ *    LT draw at vertex v  : word 0 of counter (r, v, t, 3)
  * so RR set r is a pure function of (graph, model, seed, r), whatever the launch shape.
  */
 #ifndef IMM_H
@@ -270,6 +270,60 @@ imm_status imm_server_wait(imm_server* s, uint64_t ticket, double timeout_s, int
 imm_status imm_server_stats_get(imm_server* s, imm_server_stats* out);
 /* Stops the worker (queries still pending are dropped) and frees everything. */
 imm_status imm_server_destroy(imm_server* s);
+
+/* ---- multi-round influence maximisation (gIM Sec. IV-H, Table 3) -----------------------
+ * Influence spreads in `rounds` independent rounds, round t starting from seed set S_t
+ * (|S_t| <= k); the objective is the expected number of vertices active in at least one
+ * round (CR-NAIMM, Sun et al., KDD'18, which gIM accelerates).  A multi-round RR set draws
+ * one root (the root draw of the plain set) and runs one reverse search per round t from
+ * it, in round t's live-edge instance: the edge draws use counter (r, g, t, domain) (t = 0
+ * is the plain set).  Its elements are (vertex u, round t) pairs, numbered t * n + u.
+ *
+ * imm_mr_pool_create makes a pool of such sets (1 <= rounds <= 32, rounds * n < 2^31;
+ * rounds = 1 is an ordinary pool).  On it, imm_generate_rr, imm_pool_size, imm_rr_export
+ * (elements t * n + u, sorted per set) and imm_rr_histogram (hist_out uint32[rounds * n],
+ * entry t * n + u) work as on plain pools; imm_select_seeds takes k as the seeds per round
+ * and returns rounds * k elements in selection order: each step takes, among the elements
+ * not chosen whose round holds fewer than k chosen, the one in the most uncovered sets
+ * (smallest element among equals), the greedy of a partition matroid; imm_solve_pool runs
+ * CR-NAIMM on it.  Errors as for plain pools. */
+imm_status imm_mr_pool_create(const imm_graph* g, imm_model model, uint64_t seed, int32_t rounds,
+                              imm_pool** out);
+
+/* CR-NAIMM: IMM's estimation loop and final sample (gIM Alg. 2 and 1) over multi-round RR
+ * sets, with the multi-round sample sizes (ln C(n,k) taken `rounds` times in the union
+ * bound; greedy ratio 1/2 of a partition matroid instead of 1 - 1/e when rounds > 1).
+ * seeds_out int32[rounds * k]: elements t * n + u in selection order (vertex u seeds round
+ * t).  opt->fresh_final must be 0 when rounds > 1 (IMM_EINVAL).  The result is a pure
+ * function of (g, model, opt->seed, k, rounds, eps, ell); rounds = 1 is imm_solve. */
+imm_status imm_mrim_solve(const imm_graph* g, int32_t k, int32_t rounds, double eps, double ell,
+                          imm_model model, const imm_options* opt, int32_t* seeds_out,
+                          imm_info* info);
+double imm_mr_lambda_prime(int64_t n, int64_t k, int32_t rounds, double eps, double ell);
+double imm_mr_lambda_star(int64_t n, int64_t k, int32_t rounds, double eps, double ell);
+
+/* ---- forward Monte-Carlo influence spread (gIM Sec. II-C) ----------------------------
+ * Scores a seed set by simulation: E[I(S)] is the expected number of vertices reachable
+ * from S in an instance graph (IC: each edge kept with its probability; LT: each vertex
+ * keeps at most one in-edge, chosen with its normalised weight), which gIM uses to compare
+ * solution quality.  Simulation j in [0, sims) of round t draws with its own contract,
+ * independent of the RR sets':
+ *    IC edge e (in-edge numbering) kept  : word 0 of Philox(j, e, t, 4) < thr[e], or thr[e]
+ *                                          saturated
+ *    LT vertex v keeps in-edge e          : the first e of v's in-list whose cumulative
+ *                                          threshold exceeds word 0 of Philox(j, v, t, 5)
+ * seeds (host or device, nseeds entries) are elements t * n + u (vertex u seeds round t;
+ * rounds = 1: plain vertex ids); a simulation counts the vertices reached in at least one
+ * round (the multi-round objective of Sec. IV-H).  Outputs (each may be NULL):
+ * per_sim_out uint32[sims] (host) each simulation's count, *total_out their exact sum,
+ * *mean_out the mean, *stderr_out the sample standard deviation / sqrt(sims).  The counts
+ * are a pure function of (g, model, seed, seeds, rounds, j).  The first call on a graph
+ * builds its out-edge lists (m x 8 B + (n + 1) x 8 B, kept until the graph is destroyed).
+ * Errors: IMM_EINVAL (model not encoded, rounds outside [1, 32], sims outside [0, 2^32),
+ * a seed element outside [0, rounds * n)), IMM_ENOMEM. */
+imm_status imm_spread_mc(const imm_graph* g, imm_model model, int32_t rounds, const int32_t* seeds,
+                         int32_t nseeds, int64_t sims, uint64_t seed, uint32_t* per_sim_out,
+                         int64_t* total_out, double* mean_out, double* stderr_out, void* stream);
 
 /* IMM sample-size quantities, exposed for verification (IEEE double, no FMA contraction):
  * ln C(n,k); lambda' of the LB loop; lambda* of the final sample; ell' = ell(1+ln2/ln n). */

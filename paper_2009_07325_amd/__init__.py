@@ -32,7 +32,9 @@ EXPORTS = ("imm_init", "imm_last_error", "imm_release_cached_memory", "imm_graph
            "imm_lambda_prime", "imm_lambda_star", "imm_autotune", "imm_batch_solve",
            "imm_server_create",
            "imm_server_submit",
-           "imm_server_poll", "imm_server_wait", "imm_server_stats_get", "imm_server_destroy")
+           "imm_server_poll", "imm_server_wait", "imm_server_stats_get", "imm_server_destroy",
+           "imm_mr_pool_create", "imm_mrim_solve", "imm_mr_lambda_prime", "imm_mr_lambda_star",
+           "imm_spread_mc")
 
 
 class ImmError(RuntimeError):
@@ -143,6 +145,12 @@ def lib() -> ctypes.CDLL:
             "imm_server_wait": [p, u64, dbl, p, ctypes.POINTER(ImmInfo)],
             "imm_server_stats_get": [p, ctypes.POINTER(ImmServerStats)],
             "imm_server_destroy": [p],
+            "imm_mr_pool_create": [p, ctypes.c_int, u64, i32, pp],
+            "imm_mrim_solve": [p, i32, i32, dbl, dbl, ctypes.c_int, ctypes.POINTER(ImmOptions), p,
+                               ctypes.POINTER(ImmInfo)],
+            "imm_spread_mc": [p, ctypes.c_int, i32, p, i32, i64, u64, p,
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -155,6 +163,10 @@ def lib() -> ctypes.CDLL:
         for name in ("imm_lambda_prime", "imm_lambda_star"):
             f = getattr(L, name)
             f.argtypes = [i64, i64, dbl, dbl]
+            f.restype = dbl
+        for name in ("imm_mr_lambda_prime", "imm_mr_lambda_star"):
+            f = getattr(L, name)
+            f.argtypes = [i64, i64, i32, dbl, dbl]
             f.restype = dbl
         _lib = L
     return _lib
@@ -266,8 +278,10 @@ def imm_release_cached_memory() -> None:
     _check(lib().imm_release_cached_memory())
 
 
-def imm_select_seeds(p, first: int, count: int, k: int, stream=None) -> tuple[np.ndarray, int]:
-    seeds = np.zeros(k, dtype=np.int32)
+def imm_select_seeds(p, first: int, count: int, k: int, stream=None,
+                     rounds: int = 1) -> tuple[np.ndarray, int]:
+    """k seeds per round; a multi-round pool of `rounds` rounds returns rounds * k elements."""
+    seeds = np.zeros(k * rounds, dtype=np.int32)
     cov = ctypes.c_int64()
     _check(lib().imm_select_seeds(p, first, count, k, _ptr(seeds), ctypes.byref(cov),
                                   _stream(stream)))
@@ -286,12 +300,53 @@ def imm_solve(g, k: int, eps: float, ell: float, model: int, seed: int,
 
 
 def imm_solve_pool(p, k: int, eps: float, ell: float, fresh_final: bool = False,
-                   stream=None) -> tuple[np.ndarray, dict]:
-    seeds = np.zeros(k, dtype=np.int32)
+                   stream=None, rounds: int = 1) -> tuple[np.ndarray, dict]:
+    seeds = np.zeros(k * rounds, dtype=np.int32)
     info = ImmInfo()
     _check(lib().imm_solve_pool(p, k, eps, ell, int(fresh_final), _stream(stream), _ptr(seeds),
                                 ctypes.byref(info)))
     return seeds, info.as_dict()
+
+
+def imm_mr_pool_create(g, model: int, seed: int, rounds: int):
+    out = ctypes.c_void_p()
+    _check(lib().imm_mr_pool_create(g, model, seed, rounds, ctypes.byref(out)))
+    return out
+
+
+def imm_mrim_solve(g, k: int, rounds: int, eps: float, ell: float, model: int, seed: int,
+                   stream=None) -> tuple[np.ndarray, dict]:
+    """Multi-round IM: rounds * k elements t * n + u in selection order."""
+    opt = ImmOptions(seed=seed, fresh_final=0, reserved=0, stream=_stream(stream))
+    seeds = np.zeros(k * rounds, dtype=np.int32)
+    info = ImmInfo()
+    _check(lib().imm_mrim_solve(g, k, rounds, eps, ell, model, ctypes.byref(opt), _ptr(seeds),
+                                ctypes.byref(info)))
+    return seeds, info.as_dict()
+
+
+def imm_mr_lambda_prime(n: int, k: int, rounds: int, eps: float, ell: float) -> float:
+    return lib().imm_mr_lambda_prime(n, k, rounds, eps, ell)
+
+
+def imm_mr_lambda_star(n: int, k: int, rounds: int, eps: float, ell: float) -> float:
+    return lib().imm_mr_lambda_star(n, k, rounds, eps, ell)
+
+
+def imm_spread_mc(g, model: int, seeds, sims: int, seed: int, rounds: int = 1,
+                  per_sim: bool = False, stream=None) -> dict:
+    """Forward Monte-Carlo spread of `seeds` (elements t * n + u when rounds > 1): exact
+    total of the per-simulation counts, mean and standard error (and the counts)."""
+    el = np.ascontiguousarray(seeds, dtype=np.int32)
+    ps = np.zeros(max(sims, 1), dtype=np.uint32) if per_sim else None
+    tot, mean, se = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().imm_spread_mc(g, model, rounds, _ptr(el), len(el), sims, seed, _ptr(ps),
+                               ctypes.byref(tot), ctypes.byref(mean), ctypes.byref(se),
+                               _stream(stream)))
+    out = dict(total=tot.value, mean=mean.value, stderr=se.value)
+    if per_sim:
+        out["per_sim"] = ps[:sims]
+    return out
 
 
 def imm_autotune(g, model: int, seed: int, pilot_sets: int) -> dict:
@@ -401,9 +456,16 @@ class Pool:
     handle: ctypes.c_void_p
     graph: Graph
 
+    rounds: int = 1
+
     @classmethod
     def create(cls, graph: Graph, model: int, seed: int) -> "Pool":
         return cls(imm_pool_create(graph.handle, model, seed), graph)
+
+    @classmethod
+    def create_mr(cls, graph: Graph, model: int, seed: int, rounds: int) -> "Pool":
+        """A multi-round pool: elements t * n + u over `rounds` rounds."""
+        return cls(imm_mr_pool_create(graph.handle, model, seed, rounds), graph, rounds)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -58,19 +58,23 @@ double log_binom(int64_t n, int64_t k) {
     return acc;
 }
 double ell_prime(int64_t n, double ell) { return ell * (1.0 + rt_log(2.0) / rt_log((double)n)); }
-double lambda_prime(int64_t n, int64_t k, double eps, double lp) {
+double lambda_prime(int64_t n, int64_t k, double eps, double lp, int32_t rounds) {
     const double ep = std::sqrt(2.0) * eps;
-    const double lnc = log_binom(n, k);
+    const double lnc = (double)rounds * log_binom(n, k);
     volatile double lg2n = std::log2((double)n);
     return (2.0 + 2.0 / 3.0 * ep) * (lnc + lp * rt_log((double)n) + rt_log(lg2n)) * (double)n /
            (ep * ep);
 }
-double lambda_star(int64_t n, int64_t k, double eps, double lp) {
-    const double lnc = log_binom(n, k);
+// The greedy's approximation ratio enters lambda*: 1 - 1/e for one round (IMM); for
+// several rounds the seeds form a partition matroid (at most k per round), where greedy
+// guarantees 1/2.  Both the union bound's ln C(n,k) (per round) and the ratio are the only
+// places the multi-round problem differs.
+double lambda_star(int64_t n, int64_t k, double eps, double lp, int32_t rounds) {
+    const double g = rounds == 1 ? 1.0 - 1.0 / kE : 0.5;
+    const double lnc = (double)rounds * log_binom(n, k);
     const double alpha = std::sqrt(lp * rt_log((double)n) + rt_log(2.0));
-    const double beta = std::sqrt((1.0 - 1.0 / kE) * (lnc + lp * rt_log((double)n) + rt_log(2.0)));
-    return 2.0 * (double)n * ((1.0 - 1.0 / kE) * alpha + beta) * ((1.0 - 1.0 / kE) * alpha + beta) /
-           (eps * eps);
+    const double beta = std::sqrt(g * (lnc + lp * rt_log((double)n) + rt_log(2.0)));
+    return 2.0 * (double)n * (g * alpha + beta) * (g * alpha + beta) / (eps * eps);
 }
 // gIM Alg. 2 runs i = 1 .. log2(n) - 1; we read the bound as floor(log2 n) - 1.
 int32_t estimation_rounds(int64_t n) {
@@ -80,8 +84,10 @@ int32_t estimation_rounds(int64_t n) {
 }
 
 // ---- ImmPlan ---------------------------------------------------------------------------
-imm_status ImmPlan::init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_) {
+imm_status ImmPlan::init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_,
+                         int32_t mr_) {
     if (k_ < 1 || k_ > n_) return fail(IMM_EINVAL, "k = %d outside [1, n]", k_);
+    if (mr_ < 1 || mr_ > kMaxRounds) return fail(IMM_EINVAL, "rounds = %d outside [1, %d]", mr_, kMaxRounds);
     if (!(eps_ > 0.0 && eps_ < 1.0)) return fail(IMM_EINVAL, "eps = %g outside (0, 1)", eps_);
     if (!(ell_ > 0.0)) return fail(IMM_EINVAL, "ell = %g must be > 0", ell_);
     *this = ImmPlan();
@@ -90,10 +96,11 @@ imm_status ImmPlan::init(int64_t n_, int32_t k_, double eps_, double ell_, int32
     eps = eps_;
     ell = ell_;
     fresh = fresh_;
+    mr = mr_;
     lp = ell_prime(n, ell);
     ep = std::sqrt(2.0) * eps;
-    lam1 = lambda_prime(n, k, eps, lp);
-    lam2 = lambda_star(n, k, eps, lp);
+    lam1 = lambda_prime(n, k, eps, lp, mr);
+    lam2 = lambda_star(n, k, eps, lp, mr);
     rounds = estimation_rounds(n);
     if (rounds < 1) return enter_final();
     return IMM_OK;
@@ -153,7 +160,7 @@ imm_status ImmPlan::complete(int64_t cov) {
     if ((double)n * (double)cov / (double)used >= (1.0 + ep) * x) {
         lb = (double)n * (double)cov / (double)used / (1.0 + ep);
         IMM_TRY(enter_final());
-        // a passing phase ran all k rounds over [0, used)
+        // a passing phase ran all (mr * k) greedy rounds over [0, used)
         reuse = first == 0 && upto == used;
         return IMM_OK;
     }
@@ -195,6 +202,12 @@ extern "C" imm_status imm_graph_destroy(imm_graph* g) {
     dfree(g->src);
     dfree(g->thr);
     dfree(g->cum);
+    dfree(g->lrec);
+    dfree(g->grec);
+    dfree(g->gidx);
+    dfree(g->out_off);
+    dfree(g->out_dst);
+    dfree(g->out_eid);
     delete g;
     return IMM_OK;
 }
@@ -268,6 +281,10 @@ static imm_status graph_create_impl(imm_graph* g, const int64_t* in_off, const i
         G_TRY(dalloc(&g->cum, m_pad));
         G_HIP(hipMemset(g->cum, 0, sizeof(uint32_t) * (size_t)m_pad));
         G_HIP(launch_encode_lt(n, d_off, d_w, g->cum, s));
+        G_TRY(dalloc(&g->lrec, m));
+        G_TRY(dalloc(&g->grec, 2 * m));
+        G_TRY(dalloc(&g->gidx, 2 * m));
+        G_HIP(launch_build_lt_tables(n, m, g->cum, g->src, g->vrec, g->lrec, g->grec, g->gidx, s));
         g->has_lt = true;
     }
     G_HIP(hipDeviceSynchronize());
@@ -345,11 +362,16 @@ extern "C" imm_status imm_pool_destroy(imm_pool* p) {
     p->gen.release();
     p->sel.release();
     p->launch.release();
+    for (imm_pool*& q : p->sub) {
+        if (q) imm_pool_destroy(q);
+        q = nullptr;
+    }
+    delete p->view;
     delete p;
     return IMM_OK;
 }
 
-static imm_status pool_init(imm_pool* p) {
+imm_status imm::pool_init(imm_pool* p) {
     const imm_graph* g = p->g;
     IMM_TRY(dalloc(&p->hist, g->n));
     IMM_TRY(dalloc(&p->ctr, 1));
@@ -491,6 +513,7 @@ void SelectWs::release() {
     dfree(scan_tmp);
     dfree(cursor);
     dfree(covered);
+    dfree(taken);
     dfree(keys);
     dfree(seeds);
     dfree(n_covered);
@@ -520,6 +543,7 @@ static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t
         IMM_TRY(dalloc(&w->scan_tmp, scan_tmp_elems(n)));
         IMM_TRY(dalloc(&w->cursor, n));
         IMM_TRY(dalloc(&w->n_covered, 1));
+        IMM_TRY(dalloc(&w->taken, kMaxRounds));
         IMM_TRY(halloc(&w->host_cov, 1));
     }
     if (count > w->cap_cov) {
@@ -561,9 +585,10 @@ static imm_status index_segment(imm_pool* p, SelectWs* w, const uint32_t* cnt, i
     return IMM_OK;
 }
 
-imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t k,
+imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t kr,
                                hipStream_t s, SelInst* out, bool segments) {
     const int32_t n = p->g->n;
+    const int32_t k = kr * p->rounds;        // multi-round: kr seeds per round
     IMM_TRY(ensure_select(p, w, count, k));
     const uint32_t* hsrc = nullptr;
     IMM_TRY(range_hist(p, w, first, count, &hsrc, s));
@@ -600,10 +625,14 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
     HIP_TRY(launch_fill_u32(w->covered, count, 0u, s));
     HIP_TRY(launch_fill_u64(w->keys, k, 0ull, s));
     HIP_TRY(launch_fill_u64(w->n_covered, 1, 0ull, s));
+    if (p->rounds > 1) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(w->taken), kMaxRounds, 0u, s));
     w->k = k;
     SelInst si{};
     si.n = n;
     si.k = k;
+    si.part_n = p->rounds > 1 ? p->n_base : 0;
+    si.part_k = kr;
+    si.taken = w->taken;
     si.first = first;
     si.count = count;
     si.h = w->h;
@@ -667,7 +696,7 @@ static imm_status pool_select(imm_pool* p, int64_t first, int64_t count, int32_t
     si.need = need;
     SelectWs* w = &p->sel;
     IMM_TRY(select_run(&p->launch, &w, &si, 1, s));
-    if (seeds_out) memcpy(seeds_out, w->host_seeds, sizeof(int32_t) * (size_t)k);
+    if (seeds_out) memcpy(seeds_out, w->host_seeds, sizeof(int32_t) * (size_t)w->k);
     if (covered_out) *covered_out = (int64_t)*w->host_cov;
     return IMM_OK;
 }
@@ -676,22 +705,23 @@ extern "C" imm_status imm_select_seeds(imm_pool* p, int64_t first, int64_t count
                                        int32_t* seeds_out, int64_t* covered_out, void* stream) {
     if (!p) return fail(IMM_EINVAL, "pool is NULL");
     IMM_TRY(check_range(p, first, count));
-    if (k < 1 || k > p->g->n) return fail(IMM_EINVAL, "k = %d outside [1, n]", k);
+    if (k < 1 || k > pool_vertices(p)) return fail(IMM_EINVAL, "k = %d outside [1, n]", k);
     return pool_select(p, first, count, k, seeds_out, covered_out, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------------------------
 // IMM driver
 // ------------------------------------------------------------------------------------
-static imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh,
-                          hipStream_t s, int32_t* seeds_out, imm_info* info) {
+imm_status imm::run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh,
+                        hipStream_t s, int32_t* seeds_out, imm_info* info) {
     if (!seeds_out) return fail(IMM_EINVAL, "seeds_out is NULL");
     const double t0 = now_s();
     double t_gen = 0.0, t_sel = 0.0;
     const double kernel_s0 = p->gen.kernel_s, heavy_s0 = p->gen.heavy_s;
     const int64_t launches0 = p->gen.kernel_launches, heavy0 = p->gen.heavy_launches;
+    if (p->rounds > 1 && fresh) return fail(IMM_EINVAL, "multi-round solves reuse the estimation sets");
     ImmPlan plan;
-    IMM_TRY(plan.init(p->g->n, k, eps, ell, fresh));
+    IMM_TRY(plan.init(pool_vertices(p), k, eps, ell, fresh, p->rounds));
     while (!plan.done) {
         if (plan.reuses_last()) {          // seeds_out holds that phase's seeds
             IMM_TRY(plan.complete(plan.covered));

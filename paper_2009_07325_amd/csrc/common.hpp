@@ -44,6 +44,21 @@ __device__ __forceinline__ VRec load_vrec(const IMM_GLOBAL VRec* p) {
 constexpr uint32_t kUniformBit = 0x80000000u;
 constexpr uint32_t kDegMask = 0x7FFFFFFFu;
 
+// LT in-edge record: everything one reverse-walk step needs from the edge it picks, in
+// one aligned 16-byte load -- the edge's cumulative threshold, its source, and the
+// source's in-edge range (so the next step needs no vertex-record load).
+struct alignas(16) LtRec {
+    uint32_t cum;
+    int32_t src;
+    uint32_t start;     // first in-edge of src (edge indices fit 32 bits)
+    uint32_t deg;       // in-degree of src
+};
+
+__device__ __forceinline__ LtRec load_ltrec(const IMM_GLOBAL LtRec* p) {
+    const u32x4 v = *reinterpret_cast<const IMM_GLOBAL u32x4*>(p);
+    return LtRec{v.x, (int32_t)v.y, v.z, v.w};
+}
+
 // ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) -------------------------------
 // Ten rounds of the Philox S-box on a 128-bit counter with a 64-bit key, the key advanced
 // by the Weyl constants between rounds.

@@ -151,4 +151,67 @@ hipError_t launch_encode_lt(int32_t n, const int64_t* in_off, const uint32_t* w,
     return hipGetLastError();
 }
 
+// ---- LT walk tables ---------------------------------------------------------------------
+// The pick of a walk step is the first in-edge of v whose cumulative threshold exceeds the
+// draw x (gIM Sec. III-G).  Instead of searching v's list, the walk looks its answer up in
+// a guide table (the inverse-CDF guide of Chen and Asau, 1974): v's 2d buckets split the
+// draws [0, 2^32) evenly, bucket b starting at L_b = ceil(b 2^32 / 2d), and the guide of b
+// is the first edge whose threshold exceeds L_b.  Every x of bucket b has its pick at or
+// after that edge (thresholds are non-decreasing), and it is that edge unless a threshold
+// falls inside the bucket, so the walk reads one guide entry and, rarely, the edges after
+// it: the same pick as the search, in about one dependent load.  The guide entries of v
+// sit at [2 start_v, 2 start_v + 2d), each holding the edge record of its edge and, in a
+// parallel array, the edge's position in v's list.
+
+// lrec[e] = (cum[e], src[e], range of src)
+__global__ void k_build_lrec(int64_t m, const uint32_t* __restrict__ cum, const int32_t* __restrict__ src,
+                             const VRec* __restrict__ vrec, LtRec* __restrict__ lrec) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = src[e];
+        const VRec r = vrec[u];
+        lrec[e] = LtRec{cum[e], u, (uint32_t)r.start, r.deg & kDegMask};
+    }
+}
+
+// One wave per vertex: the guide entry of each of its 2d buckets by a binary search over
+// its thresholds (the last is saturated, so a qualifying edge always exists).
+__global__ void k_build_guide(int32_t n, const VRec* __restrict__ vrec, const uint32_t* __restrict__ cum,
+                              const LtRec* __restrict__ lrec, LtRec* __restrict__ grec,
+                              uint32_t* __restrict__ gidx) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        const int64_t s = vrec[v].start;
+        const uint32_t d = vrec[v].deg & kDegMask;
+        const uint64_t nb = 2ull * d;
+        for (uint64_t b = lane; b < nb; b += kWave) {
+            const uint64_t lb = ((b << 32) + nb - 1) / nb;        // ceil(b 2^32 / 2d)
+            uint32_t lo = 0, hi = d - 1;                          // first qualifying in [lo, hi]
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t c = cum[s + mid];
+                if (c == kAlways || (uint64_t)c > lb) hi = mid; else lo = mid + 1;
+            }
+            grec[2 * s + (int64_t)b] = lrec[s + lo];
+            gidx[2 * s + (int64_t)b] = lo;
+        }
+    }
+}
+
+hipError_t launch_build_lt_tables(int32_t n, int64_t m, const uint32_t* cum, const int32_t* src,
+                                  const VRec* vrec, LtRec* lrec, LtRec* grec, uint32_t* gidx,
+                                  hipStream_t s) {
+    if (m > 0) {
+        int64_t blocks = (m + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        k_build_lrec<<<(unsigned)blocks, 256, 0, s>>>(m, cum, src, vrec, lrec);
+    }
+    int64_t blocks = ((int64_t)n * kWave + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_build_guide<<<(unsigned)blocks, 256, 0, s>>>(n, vrec, cum, lrec, grec, gidx);
+    return hipGetLastError();
+}
+
 }  // namespace imm

@@ -115,8 +115,10 @@ inline unsigned long long sum64(const unsigned long long* v) {
 // ---- IMM sample sizes and the LB / theta state machine --------------------------------
 double log_binom(int64_t n, int64_t k);
 double ell_prime(int64_t n, double ell);
-double lambda_prime(int64_t n, int64_t k, double eps, double lp);
-double lambda_star(int64_t n, int64_t k, double eps, double lp);
+// `rounds` > 1: the multi-round problem (gIM Sec. IV-H), whose union bound runs over
+// C(n,k)^rounds seed collections and whose greedy (a partition matroid) guarantees 1/2.
+double lambda_prime(int64_t n, int64_t k, double eps, double lp, int32_t rounds = 1);
+double lambda_star(int64_t n, int64_t k, double eps, double lp, int32_t rounds = 1);
 int32_t estimation_rounds(int64_t n);
 
 // One IMM solve as a sequence of selections (gIM Alg. 2, then Alg. 1).  next() names the
@@ -125,7 +127,8 @@ int32_t estimation_rounds(int64_t n);
 // this one object, so they all compute the same doubles in the same order.
 struct ImmPlan {
     int64_t n = 0;
-    int32_t k = 0;
+    int32_t k = 0;                 // seeds per round
+    int32_t mr = 1;                // rounds of a multi-round solve (selections take mr * k)
     double eps = 0, ell = 0;
     int32_t fresh = 0;
     double lp = 0, ep = 0, lam1 = 0, lam2 = 0;
@@ -144,7 +147,8 @@ struct ImmPlan {
     // so that phase's seeds and coverage are the final ones and no selection is run.
     bool reuse = false;
 
-    imm_status init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_);
+    imm_status init(int64_t n_, int32_t k_, double eps_, double ell_, int32_t fresh_,
+                    int32_t mr_ = 1);
     imm_status next(int64_t* gen_upto, int64_t* sel_first, int64_t* sel_count);
     imm_status complete(int64_t cov);
     // Smallest coverage of the current estimation phase's selection that passes its test
@@ -178,9 +182,16 @@ struct imm_graph {
     int32_t* src = nullptr;
     uint32_t* thr = nullptr;     // IC thresholds (padded to a multiple of 4 edges)
     uint32_t* cum = nullptr;     // LT cumulative thresholds
+    imm::LtRec* lrec = nullptr;  // LT walk tables: edge records (m), guide records (2m)
+    imm::LtRec* grec = nullptr;
+    uint32_t* gidx = nullptr;    // ... and guide positions (2m)
     bool has_ic = false, has_lt = false;
     bool ic_uniform = false;     // every vertex has one common IC threshold
     int cus = 0;
+    // out-edge lists, built on first use by the forward spread simulations
+    int64_t* out_off = nullptr;  // n + 1
+    int32_t* out_dst = nullptr;  // m
+    uint32_t* out_eid = nullptr; // m: in-edge index
 };
 
 namespace imm {
@@ -211,6 +222,7 @@ struct SelectWs {
     bool snap_valid = false;
     int64_t cap_cov = 0;
     uint32_t* covered = nullptr;
+    int32_t* taken = nullptr;                 // kMaxRounds partition counts
     int64_t cap_k = 0;
     unsigned long long* keys = nullptr;
     int32_t* seeds = nullptr;
@@ -286,6 +298,17 @@ struct imm_pool {
     imm_model model = IMM_IC;
     uint64_t seed = 0;
     int64_t count = 0;
+    uint32_t round = 0;                 // third counter word of this pool's edge draws
+
+    // Multi-round pool (rounds > 1, gIM Sec. IV-H): set r is the union over t of round
+    // pool sub[t]'s set r as elements t * n_base + u.  Generation extends the round pools
+    // and lays their sets side by side in this pool's own arrays (contiguous, index
+    // order); g is then `view`, a graph record with n = rounds * n_base and no arrays, so
+    // histogram, index and selection run over the element space unchanged.
+    int32_t rounds = 1;
+    int32_t n_base = 0;
+    imm_pool* sub[imm::kMaxRounds] = {};
+    imm_graph* view = nullptr;
 
     int64_t cap_sets = 0;
     int64_t* rr_start = nullptr;
@@ -314,6 +337,16 @@ namespace imm {
 imm_status gen_run(GenCtx* c, imm_pool* const* pools, const int64_t* upto, int32_t count,
                    hipStream_t s);
 imm_status pool_generate(imm_pool* p, int64_t upto, hipStream_t s);
+// Device arrays and generation context of a new pool (p->g, model, seed set).
+imm_status pool_init(imm_pool* p);
+// One IMM solve on pool p (CR-NAIMM on a multi-round pool): gIM Alg. 2 then Alg. 1.
+// seeds_out holds p->rounds * k entries.
+imm_status run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_t fresh, hipStream_t s,
+                   int32_t* seeds_out, imm_info* info);
+// Multi-round pools: lays out sets [p->count, upto) from the round pools (mrim.cpp).
+imm_status mr_merge(imm_pool* p, int64_t upto, hipStream_t s);
+// Vertices of the graph a pool draws from (the part size of a multi-round pool).
+inline int64_t pool_vertices(const imm_pool* p) { return p->rounds > 1 ? p->n_base : p->g->n; }
 imm_status check_range(const imm_pool* p, int64_t first, int64_t count);
 
 // Launches the per-selection setup kernels (counts, inverted index, clears) on `s` and

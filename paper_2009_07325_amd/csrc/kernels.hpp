@@ -49,6 +49,10 @@ hipError_t launch_build_vrec(int32_t n, const int64_t* in_off, const uint32_t* t
                              unsigned int* n_mixed, hipStream_t s);
 hipError_t launch_encode_lt(int32_t n, const int64_t* in_off, const uint32_t* w, uint32_t* cum,
                             hipStream_t s);
+// LT walk tables: edge records lrec[m], guide records grec[2m] and positions gidx[2m].
+hipError_t launch_build_lt_tables(int32_t n, int64_t m, const uint32_t* cum, const int32_t* src,
+                                  const VRec* vrec, LtRec* lrec, LtRec* grec, uint32_t* gidx,
+                                  hipStream_t s);
 
 // ---- rr_gen.hip ---------------------------------------------------------------------
 // One (graph, pool) of a generation launch.  A launch covers any number of instances:
@@ -59,8 +63,13 @@ struct GenInst {
     const int32_t* src;
     const uint32_t* thr;     // IC per-edge thresholds (padded to a multiple of 4 edges)
     const uint32_t* cum;     // LT cumulative thresholds
+    const LtRec* lrec;       // LT walk tables (edge records, guide records and positions)
+    const LtRec* grec;
+    const uint32_t* gidx;
     int32_t n;
     uint32_t k0, k1;         // Philox key (pool seed)
+    uint32_t round;          // third counter word of the edge draws (round of a
+                             // multi-round set; 0 for plain sets)
     // RR indices of this launch: first + j, or list[j], for j in [0, count)
     int64_t first;
     const uint32_t* list;
@@ -107,7 +116,10 @@ constexpr int64_t kArenaWords = (int64_t)16 << 20;   // handoff arena: 64 MiB of
 hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s);   // 256-thread blocks
 // block: threads per heavy set, 64, 128, 256 or 1024
 hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s);
+// big: walks too long for the on-chip list (HBM list and bitmap, one walk per wave);
+// otherwise the first pass (several walks per wave, guide-table steps)
 hipError_t launch_lt(const GenLaunch& a, bool big, int grid, hipStream_t s);
+int lt_walks_per_block();          // walks one block of the first LT pass runs at once
 int rr_light_capacity();
 // Sums each instance's spread counters into out[i] and clears its n_capacity.
 hipError_t launch_pool_summary(const GenInst* inst, int32_t ninst, PoolSummary* out,
@@ -143,6 +155,8 @@ hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStre
 // step of every instance, a grid barrier.
 // Inverted-index segments one selection may read (sets of successive estimation phases).
 constexpr int kMaxSegs = 16;
+// Rounds of a multi-round RR set at most (parts of the selection's partition matroid).
+constexpr int kMaxRounds = 32;
 
 struct SelInst {
     int32_t n;
@@ -168,7 +182,13 @@ struct SelInst {
     // of every segment j, seg_inv[j][seg_off[j][v] .. seg_off[j][v + 1]).  nseg == 1 means
     // inv_off / inv alone (the only form multi-instance launches accept).
     int32_t nseg;
+    // Partition matroid (multi-round sets, single-instance launches only): element v
+    // belongs to part v / part_n, and a part whose taken[] count has reached part_k
+    // offers no more elements.  part_n == 0: no constraint.
+    int32_t part_n;
+    int32_t part_k;
     int32_t pad0;
+    int32_t* taken;                // per part (at most kMaxRounds), zeroed
     const int64_t* seg_off[kMaxSegs];
     const uint32_t* seg_inv[kMaxSegs];
 };
@@ -184,6 +204,55 @@ int select_coop_grid();            // blocks of the cooperative launch (co-resid
 int select_max_inst();             // instances one cooperative launch can take
 hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
                               hipStream_t s);
+// ---- mr_sets.hip -----------------------------------------------------------------------
+// The round pools of a multi-round pool (gIM Sec. IV-H): round t's sets, read by the merge.
+struct MrSrc {
+    const int64_t* start[kMaxRounds];
+    const int32_t* len[kMaxRounds];
+    const int32_t* ids[kMaxRounds];
+    int32_t rounds;
+    int32_t n_base;              // vertices of the graph: element of (u, t) is t * n_base + u
+};
+// sizes[i] = sum over t of the size of round t's set first + i.
+hipError_t launch_mr_sizes(const MrSrc& src, int64_t first, int64_t count, int64_t* sizes,
+                           hipStream_t s);
+// Writes multi-round set first + i at ids[base + off[i] ...): the members of round 0, then
+// round 1, ..., each member u of round t as t * n_base + u; sets rr_start / rr_len.
+hipError_t launch_mr_copy(const MrSrc& src, int64_t first, int64_t count, const int64_t* off,
+                          int64_t base, int64_t* rr_start, int32_t* rr_len, int32_t* ids,
+                          hipStream_t s);
+
+// ---- fwd_mc.hip ----------------------------------------------------------------------
+// Out-edge lists of a graph, from its in-edge lists: out-degrees, then (after a scan into
+// out_off) each in-edge (u -> v, e) placed in u's list as (v, e).
+hipError_t launch_out_degree(int64_t m, const int32_t* src, uint32_t* deg, hipStream_t s);
+hipError_t launch_out_scatter(int32_t n, const VRec* vrec, const int32_t* src, const int64_t* out_off,
+                              uint32_t* cursor, int32_t* out_dst, uint32_t* out_eid, hipStream_t s);
+// Forward Monte-Carlo simulations [0, sims) from a set of seed elements t * n + u.
+struct FwdLaunch {
+    const VRec* vrec;
+    const uint32_t* w;            // IC thresholds or LT cumulative thresholds
+    const int64_t* out_off;
+    const int32_t* out_dst;
+    const uint32_t* out_eid;      // in-edge index of each out-edge
+    int32_t n;
+    int32_t model;                // 0 IC, 1 LT
+    int32_t rounds;
+    uint32_t k0, k1;              // Philox key
+    const int32_t* elems;
+    int32_t nelem;
+    int64_t sims;
+    unsigned int* work;           // simulation cursor (zeroed)
+    uint32_t* counts;             // per simulation: vertices reached in some round
+    unsigned long long* sums;     // or null: [0] += count, [1] += count^2 per simulation
+    uint32_t* vis;                // per slot: bitmap of the current round's search
+    uint32_t* uvis;               // per slot: bitmap of the vertices reached so far (rounds > 1)
+    int32_t* list;                // per slot: the round's reached vertices
+    int32_t* ulist;               // per slot: vertices reached so far (rounds > 1)
+    int64_t vis_words, list_stride;
+};
+hipError_t launch_spread_fwd(const FwdLaunch& a, int grid, hipStream_t s);
+
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

@@ -10,7 +10,8 @@
 //
 // LT (gIM Sec. III-G): RR set r is the reverse walk from root(r) in which each vertex picks
 // at most one in-edge (the first cumulative threshold above its draw); the walk stops at a
-// vertex with no in-edge, no pick, or a pick already on the walk.
+// vertex with no in-edge, no pick, or a pick already on the walk.  Walks run kLtWalks to a
+// wave (k_lt_groups), each step one lookup in the vertex's guide table.
 //
 // Work split (the role of gIM's N_b persistent blocks, Alg. 6 / Eq. 5).  On skewed graphs
 // the in-edges examined per set span five orders of magnitude and ~1% of the sets carry
@@ -242,14 +243,15 @@ struct GraphView {
     const IMM_GLOBAL uint32_t* w;       // IC thresholds or LT cumulative thresholds
     uint32_t k0, k1;
     int32_t n;
+    uint32_t t;                         // round word of the edge draws
 };
 
 __device__ __forceinline__ GraphView ic_view(const GenInst& I) {
-    return GraphView{global(I.vrec), global(I.src), global(I.thr), I.k0, I.k1, I.n};
+    return GraphView{global(I.vrec), global(I.src), global(I.thr), I.k0, I.k1, I.n, I.round};
 }
 
 __device__ __forceinline__ GraphView lt_view(const GenInst& I) {
-    return GraphView{global(I.vrec), global(I.src), global(I.cum), I.k0, I.k1, I.n};
+    return GraphView{global(I.vrec), global(I.src), global(I.cum), I.k0, I.k1, I.n, I.round};
 }
 
 // Draws the in-edges of group g (edges 4g .. 4g+3) for set r; bit j of the result is set
@@ -258,7 +260,7 @@ __device__ __forceinline__ GraphView lt_view(const GenInst& I) {
 __device__ __forceinline__ uint32_t live_bits(const GraphView& a, uint32_t r, uint32_t g,
                                               uint32_t s, uint32_t e_end, bool uniform_thr,
                                               uint32_t uthr) {
-    const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, a.k0, a.k1);
+    const Ctr4 x = philox10(Ctr4{r, g, a.t, kDomainIC}, a.k0, a.k1);
     const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
     // edge 4g + j is in the vertex's list iff its offset 4g + j - s (mod 2^32) is below d
     const uint32_t d = e_end - s, o = (g << 2) - s;
@@ -282,7 +284,7 @@ __device__ __forceinline__ uint32_t live_bits(const GraphView& a, uint32_t r, ui
 // vertex with one threshold for its whole in-list): no per-edge range or threshold work.
 __device__ __forceinline__ void live_masks_interior(const GraphView& a, uint32_t r, uint32_t g,
                                                     uint32_t t, uint64_t m[4]) {
-    const Ctr4 x = philox10(Ctr4{r, g, 0u, kDomainIC}, a.k0, a.k1);
+    const Ctr4 x = philox10(Ctr4{r, g, a.t, kDomainIC}, a.k0, a.k1);
     m[0] = ballot(x.x < t);
     m[1] = ballot(x.y < t);
     m[2] = ballot(x.z < t);
@@ -749,7 +751,7 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
                     // scalar work per chunk cut to the loop control and the live-edge test.
                     uint32_t gi = g;
                     for (; c + 1 < c_hi; c += kHeavyWaves, gi += (uint32_t)(kHeavyWaves * kWave)) {
-                        const Ctr4 x = philox10(Ctr4{r, gi, 0u, kDomainIC}, a.k0, a.k1);
+                        const Ctr4 x = philox10(Ctr4{r, gi, a.t, kDomainIC}, a.k0, a.k1);
                         // one compare for "any live edge in the wave"; the per-word
                         // ballots only when there is one (rare on hub vertices)
                         const uint32_t lo = min(min(x.x, x.y), min(x.z, x.w));
@@ -895,26 +897,26 @@ __device__ __forceinline__ int64_t lt_pick(const GraphView& a, int64_t s, int64_
     return -1;
 }
 
-template <bool kBig>
-__global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
-    __shared__ int32_t lds_list[kWavesPerBlock][kBig ? 1 : kLightCap];
+// Walks too long for the on-chip list (more than kLtCap members): one walk per wave, its
+// members in an HBM list and a visited bitmap (restarted from the root).
+__global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
-    uint32_t* vis = (kBig ? G.hvisited : G.visited) + slot * G.vis_words;
-    int32_t* list = kBig ? G.hlist + slot * G.list_stride : lds_list[wib];
+    uint32_t* vis = G.hvisited + slot * G.vis_words;
+    int32_t* list = G.hlist + slot * G.list_stride;
     WaveState ws;
 
     int32_t inst;
     uint32_t r;
     while (next_set(G, ws, inst, r)) {
         const GraphView a = lt_view(G.inst[inst]);
-        const int32_t cap = kBig ? a.n : kLightCap;
+        const int32_t cap = a.n;
         const uint32_t k0 = a.k0, k1 = a.k1;
         int32_t v = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
         if (lane == 0) {
             list[0] = v;
-            if (kBig) vis_test_and_set(vis, v);
+            vis_test_and_set(vis, v);
         }
         int32_t size = 1;
         uint64_t examined = 0;
@@ -924,38 +926,154 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt(GenLaunch G) {
             const uint32_t d = rec.deg & kDegMask;
             if (d == 0) break;
             examined += d;
-            const uint32_t x = philox10(Ctr4{r, (uint32_t)v, 0u, kDomainLT}, k0, k1).x;
+            const uint32_t x = philox10(Ctr4{r, (uint32_t)v, a.t, kDomainLT}, k0, k1).x;
             int32_t u = 0;
             const int64_t j = lt_pick(a, rec.start, rec.start + d, x, &u);
             if (j < 0) break;
             bool fresh = false;
-            if (kBig) {
-                if (lane == 0) fresh = vis_test_and_set(vis, u);
-                fresh = __shfl(fresh, 0, kWave);
-            } else {
-                // the walk so far is the wave's LDS list: a revisit is a match in it
-                bool seen = false;
-                wave_sync();
-                for (int32_t i = lane; i < size; i += kWave) seen |= list[i] == u;
-                fresh = ballot(seen) == 0;
-            }
+            if (lane == 0) fresh = vis_test_and_set(vis, u);
+            fresh = __shfl(fresh, 0, kWave);
             if (!fresh) break;
             if (size + 1 > cap) {
                 abandon = true;
-                if (kBig && lane == 0) vis_clear(vis, u);
+                if (lane == 0) vis_clear(vis, u);
                 break;
             }
             if (lane == 0) list[size] = u;
             ++size;
             v = u;
         }
-        if (kBig) __threadfence(); else wave_sync();
+        __threadfence();
         if (abandon) push_heavy(G, ws, inst, r);
         else place_wave(G, ws, slot, inst, r, list, size, examined);
-        if (kBig) {
-            for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
-            vis_fence();
+        for (int32_t i = lane; i < size; i += kWave) vis_clear(vis, list[i]);
+        vis_fence();
+        wave_sync();
+    }
+    wave_exit(G, ws, slot);
+}
+
+// ------------------------------------------------------------------------------------
+// LT: the first pass of every launch.  A group of kLtGroup lanes runs one walk (kLtWalks
+// walks per wave), its members in an LDS list that is also its revisit test: the group's
+// lanes compare the picked vertex with the list, kLtGroup entries per step of the scan.
+// A step reads the pick from v's guide table (graph.hip): one 16-byte record gives the
+// picked edge's threshold (to confirm the pick), its source, and the source's in-edge
+// range, so consecutive steps are one dependent load apart.  The group's lanes compute
+// the same values (its draw, its loads, broadcast to the group); the wave places finished
+// walks one at a time.  Walks longer than kLtCap members are redrawn by k_rr_lt_hbm.
+// ------------------------------------------------------------------------------------
+constexpr int kLtGroup = 16;
+constexpr int kLtWalks = kWave / kLtGroup;
+constexpr int kLtCap = 512;
+
+__device__ __forceinline__ bool lt_ok(uint32_t c, uint32_t x) { return c == kAlways || x < c; }
+
+__global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
+    __shared__ int32_t lists[kWavesPerBlock][kLtWalks][kLtCap];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    const int grp = lane / kLtGroup, gl = lane % kLtGroup;
+    const uint64_t gmask = 0xFFFFull << (grp * kLtGroup);
+    int32_t* list = lists[wib][grp];
+    const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
+    WaveState ws;
+
+    // the group's walk (the same values in each of its lanes)
+    bool active = false;
+    int32_t inst = 0, v = 0, size = 0;
+    uint32_t r = 0, start = 0, deg = 0, k0 = 0, k1 = 0, t = 0;
+    uint64_t examined = 0;
+    const IMM_GLOBAL LtRec* grec = nullptr;
+    const IMM_GLOBAL uint32_t* gidx = nullptr;
+    const IMM_GLOBAL LtRec* lrec = nullptr;
+    bool more = true;                      // the launch still has RR indices (uniform)
+
+    for (;;) {
+        // idle groups take the launch's next RR indices, one each
+        uint64_t idle = ballot(!active && gl == 0);
+        while (idle && more) {
+            int32_t wi;
+            uint32_t wr;
+            if (!next_set(G, ws, wi, wr)) {
+                more = false;
+                break;
+            }
+            const int g_new = (__ffsll((unsigned long long)idle) - 1) / kLtGroup;
+            idle &= idle - 1;
+            if (grp == g_new) {
+                const GenInst& I = G.inst[wi];
+                inst = wi;
+                r = wr;
+                grec = global(I.grec);
+                gidx = global(I.gidx);
+                lrec = global(I.lrec);
+                k0 = I.k0;
+                k1 = I.k1;
+                t = I.round;
+                v = (int32_t)root_of(r, (uint32_t)I.n, k0, k1);
+                const VRec rec = load_vrec(global(I.vrec) + v);
+                start = (uint32_t)rec.start;
+                deg = rec.deg & kDegMask;
+                if (gl == 0) list[0] = v;
+                size = 1;
+                examined = 0;
+                active = true;
+            }
         }
+        if (ballot(active) == 0) break;     // no walk left and no index left
+        wave_sync();
+        // one step of every walk
+        bool done = false, abandon = false;
+        if (active) {
+            if (deg == 0) {
+                done = true;
+            } else {
+                examined += deg;
+                const uint32_t x = philox10(Ctr4{r, (uint32_t)v, t, kDomainLT}, k0, k1).x;
+                const int64_t gi = 2 * (int64_t)start + (int64_t)(((uint64_t)x * (2ull * deg)) >> 32);
+                LtRec rec = load_ltrec(grec + gi);
+                if (!lt_ok(rec.cum, x)) {
+                    // a threshold inside the bucket: the pick is one of the next edges
+                    // (the last edge of a list is saturated, so the scan ends within it)
+                    uint32_t pos = gidx[gi];
+                    do {
+                        ++pos;
+                        rec = load_ltrec(lrec + start + pos);
+                    } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
+                }
+                const int32_t u = rec.src;
+                bool hit = false;
+                for (int32_t i = gl; i < size; i += kLtGroup) hit |= list[i] == u;
+                if ((ballot(hit) & gmask) != 0) {
+                    done = true;                    // u is already on the walk
+                } else if (size >= kLtCap) {
+                    done = true;
+                    abandon = true;
+                } else {
+                    if (gl == 0) list[size] = u;
+                    ++size;
+                    v = u;
+                    start = rec.start;
+                    deg = rec.deg;
+                }
+            }
+        }
+        wave_sync();
+        // finished walks, one group at a time
+        uint64_t fin = ballot(done && gl == 0);
+        while (fin) {
+            const int b = __ffsll((unsigned long long)fin) - 1;
+            fin &= fin - 1;
+            const int32_t fi = __builtin_amdgcn_readlane(inst, b);
+            const uint32_t fr = __builtin_amdgcn_readlane(r, b);
+            const int32_t fs = __builtin_amdgcn_readlane(size, b);
+            const uint64_t fe = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(examined >> 32), b) << 32) |
+                                __builtin_amdgcn_readlane((uint32_t)examined, b);
+            if (__builtin_amdgcn_readlane((int)abandon, b)) push_heavy(G, ws, fi, fr);
+            else place_wave(G, ws, slot, fi, fr, lists[wib][b / kLtGroup], fs, fe);
+        }
+        if (done) active = false;
         wave_sync();
     }
     wave_exit(G, ws, slot);
@@ -981,10 +1099,12 @@ hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t 
 }
 
 hipError_t launch_lt(const GenLaunch& a, bool big, int grid, hipStream_t s) {
-    if (big) k_rr_lt<true><<<grid, kBlock, 0, s>>>(a);
-    else k_rr_lt<false><<<grid, kBlock, 0, s>>>(a);
+    if (big) k_rr_lt_hbm<<<grid, kBlock, 0, s>>>(a);
+    else k_lt_groups<<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
+
+int lt_walks_per_block() { return kWavesPerBlock * kLtWalks; }
 
 int gen_blocks_per_cu(int which) {
     int nb = 0;
@@ -995,8 +1115,8 @@ int gen_blocks_per_cu(int which) {
         case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<256>, 256, 0); break;
         case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<128>, 128, 0); break;
         case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<64>, 64, 0); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<false>, kBlock, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt<true>, kBlock, 0); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lt_groups, kBlock, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt_hbm, kBlock, 0); break;
     }
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;

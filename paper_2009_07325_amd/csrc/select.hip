@@ -425,6 +425,13 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 best = 0;
             }
             const int32_t prev = round > 0 ? ld_co(global(I.seeds) + round - 1) : -1;
+            // partition matroid: the parts that already hold part_k chosen elements
+            uint64_t full = 0;
+            if (I.part_n > 0) {
+                const int32_t parts = I.n / I.part_n;
+                const int32_t tk = lane < parts ? ld_co(global(I.taken) + lane) : 0;
+                full = ballot(lane < parts && tk >= I.part_k);
+            }
             IMM_GLOBAL int32_t* h = global(I.h);
             // up to kArgGroup of the block's successive tiles of this instance are loaded
             // together
@@ -445,6 +452,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                     st_co(h + v, -1);
                     c[j] = -1;
                 }
+                if (full != 0 && c[j] >= 0 && ((full >> ((uint32_t)v / (uint32_t)I.part_n)) & 1ull))
+                    c[j] = -1;
                 if (c[j] >= 0) {
                     const unsigned long long key = ((unsigned long long)(uint32_t)(c[j] + 1) << 32) |
                                                    (unsigned long long)(0xFFFFFFFFu - (uint32_t)v);
@@ -486,7 +495,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                     ent_beg[tid] = beg;
                     cnt = global(I.inv_off)[u + 1] - beg;
                 }
-                if (blockIdx.x == 0) st_co(global(I.seeds) + round, u);
+                if (blockIdx.x == 0) {
+                    st_co(global(I.seeds) + round, u);
+                    if (I.part_n > 0) atomic_add_agent(global(I.taken) + u / I.part_n, 1);
+                }
             }
         }
         if (!__syncthreads_or(live)) return;            // every instance finished or stopped

@@ -58,3 +58,44 @@ void synth_hash_keys(const int64_t* keys, int64_t count, uint64_t seed, uint64_t
     #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < count; ++j) out[j] = draw64(seed, (uint64_t)keys[j], 63);
 }
+
+/* Barabasi-Albert preferential attachment (the density sweep of gIM Sec. IV-F): a clique
+ * of r0 = r + 1 vertices, then vertices r0 .. n-1 one at a time, each joined to r distinct
+ * earlier vertices chosen with probability proportional to their current degree (a
+ * uniform entry of the list of all edge endpoints so far; a repeated choice is drawn
+ * again).  Writes the undirected edges (src[i], dst[i]), new vertex first; returns their
+ * number, r0 (r0 - 1) / 2 + (n - r0) r.  Sequential by construction. */
+int64_t synth_ba(int32_t n, int32_t r, uint64_t seed, int32_t* src, int32_t* dst, int32_t* ends) {
+    const int32_t r0 = r + 1;
+    int64_t m = 0, ne = 0;
+    for (int32_t a = 0; a < r0 && a < n; ++a)
+        for (int32_t b = 0; b < a; ++b) {
+            src[m] = a;
+            dst[m] = b;
+            ++m;
+            ends[ne++] = a;
+            ends[ne++] = b;
+        }
+    for (int32_t v = r0; v < n; ++v) {
+        const int64_t base = ne;          /* targets of v are chosen among [0, base) */
+        uint64_t attempt = 0;
+        for (int32_t j = 0; j < r; ++j) {
+            int32_t t;
+            for (;;) {
+                uint64_t w = draw64(seed, (uint64_t)v, attempt++ & 63);
+                if (attempt > 64) w = mix64(w ^ attempt);
+                t = ends[(int64_t)(((w & 0xFFFFFFFFull) * (uint64_t)base) >> 32)];
+                int dup = 0;
+                for (int32_t q = 0; q < j; ++q)
+                    if (dst[m - j + q] == t) { dup = 1; break; }
+                if (!dup) break;
+            }
+            src[m] = v;
+            dst[m] = t;
+            ++m;
+            ends[ne++] = v;
+            ends[ne++] = t;
+        }
+    }
+    return m;
+}

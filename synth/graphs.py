@@ -54,6 +54,8 @@ def _native():
         lib.synth_rmat_draw.argtypes = [i32, i64, u64, i64, i64, u32, u32, u32, p, p]
         lib.synth_er_draw.argtypes = [i64, u64, i64, i64, p, p]
         lib.synth_hash_keys.argtypes = [p, i64, u64, p]
+        lib.synth_ba.argtypes = [i32, i32, u64, p, p, p]
+        lib.synth_ba.restype = i64
         _lib = lib
     return _lib
 
@@ -171,6 +173,24 @@ def rmat(scale: int, m: int, seed: int, a=0.57, b=0.19, c=0.19, n: int | None = 
         progress("in-edge CSR built")
     return Graph(n, in_off, in_src, name=f"rmat_s{scale}_n{n}_m{m}",
                  meta=dict(kind="rmat", scale=scale, seed=seed, abcd=(a, b, c, 1 - a - b - c)))
+
+
+def barabasi_albert(n: int, r: int, seed: int) -> Graph:
+    """Barabasi-Albert graph (preferential attachment, r edges per new vertex, starting
+    from a clique of r + 1), the density family of gIM Sec. IV-F; each undirected edge
+    becomes two directed edges."""
+    if r < 1 or n < r + 2:
+        raise ValueError("infeasible Barabasi-Albert graph")
+    r0 = r + 1
+    mu = r0 * (r0 - 1) // 2 + (n - r0) * r
+    src = np.empty(mu, dtype=np.int32)
+    dst = np.empty(mu, dtype=np.int32)
+    ends = np.empty(2 * mu, dtype=np.int32)
+    got = _native().synth_ba(n, r, seed, src.ctypes.data, dst.ctypes.data, ends.ctypes.data)
+    assert got == mu
+    del ends
+    in_off, in_src = _to_in_csr(n, np.concatenate([src, dst]), np.concatenate([dst, src]))
+    return Graph(n, in_off, in_src, name=f"ba_n{n}_r{r}", meta=dict(kind="ba", r=r, seed=seed))
 
 
 def weighted_cascade(g: Graph) -> np.ndarray:

@@ -56,3 +56,17 @@ def test_no_cpu_fallback_in_binding():
             imm.lib()
     finally:
         imm.LIB_PATH, imm._lib = saved
+
+
+@pytest.mark.parametrize("n,k,rounds,eps,ell", [
+    (1000, 10, 5, 0.1, 1.0), (1 << 20, 50, 3, 0.2, 1.0), (4096, 1, 2, 0.5, 1.0),
+    (77_777, 33, 32, 0.07, 2.0), (1000, 10, 1, 0.1, 1.0)])
+def test_multi_round_sample_sizes_match_oracle_bitwise(oracle_lib, n, k, rounds, eps, ell):
+    """The CR-NAIMM sample sizes (gIM Sec. IV-H) of the library's host code and the
+    oracle's agree bit for bit; with one round they are IMM's."""
+    import paper_2009_07325_amd as imm
+    assert imm.imm_mr_lambda_prime(n, k, rounds, eps, ell) == oracle_lib.mr_lambda_prime(n, k, rounds, eps, ell)
+    assert imm.imm_mr_lambda_star(n, k, rounds, eps, ell) == oracle_lib.mr_lambda_star(n, k, rounds, eps, ell)
+    if rounds == 1:
+        assert imm.imm_mr_lambda_star(n, k, 1, eps, ell) == imm.imm_lambda_star(n, k, eps, ell)
+        assert imm.imm_mr_lambda_prime(n, k, 1, eps, ell) == imm.imm_lambda_prime(n, k, eps, ell)
