@@ -164,6 +164,31 @@ imm_status imm_rr_histogram(const imm_pool* p, int64_t first, int64_t count,
 imm_status imm_select_seeds(imm_pool* p, int64_t first, int64_t count, int32_t k,
                             int32_t* seeds_out, int64_t* covered_out, void* stream);
 
+/* ---- selection without allocation ----------------------------------------------------
+ * For callers that cannot allocate (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the selection of imm_select_seeds, with identical
+ * results, whose whole workspace (counters, inverted index, covered flags, argmax keys,
+ * launch descriptor and grid barrier) lives in a static device array of
+ * IMM_NOALLOC_SCRATCH_BYTES that each device holds from the library's load until the
+ * process ends.  Calls no hipMalloc, hipFree or pinned-host allocation; the seeds and the
+ * covered count are copied straight into the caller's (pageable) host memory.
+ *   p, first, count, k   as imm_select_seeds (multi-round pools: k per round)
+ *   seeds_out            int32[k x rounds], host, required
+ *   covered_out          int64, host, or NULL
+ * The workspace needs 20 n + 4 count + 4 (ids held by the pool) + 12 k bytes, plus 4 n
+ * when the range is not the pool's whole prefix, plus a few KiB
+ * (imm_select_noalloc_bytes reports the exact figure); larger requests return
+ * IMM_ECAPACITY before anything runs.  All calls on one device share its array: calls
+ * that overlap on one device (other host threads, other streams) race and must not be
+ * issued.  imm_init(device) looks the array up for that device; otherwise the first call
+ * on a device does.  Synchronises `stream`. */
+#define IMM_NOALLOC_SCRATCH_BYTES (64LL * 1024 * 1024)
+imm_status imm_select_seeds_noalloc(const imm_pool* p, int64_t first, int64_t count, int32_t k,
+                                    int32_t* seeds_out, int64_t* covered_out, void* stream);
+/* Bytes of workspace imm_select_seeds_noalloc needs for these arguments (-1 for a NULL
+ * pool or a negative count). */
+int64_t imm_select_noalloc_bytes(const imm_pool* p, int64_t first, int64_t count, int32_t k);
+
 /* IMM on graph g (gIM Alg. 2 then Alg. 1): estimate LB, sample theta = lambda* / LB RR sets,
  * select k seeds.  0 < eps < 1, ell > 0, 1 <= k <= n.  seeds_out int32[k].  The result is
  * a pure function of (g, model, opt->seed, k, eps, ell, opt->fresh_final). */

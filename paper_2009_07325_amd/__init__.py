@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libimm.so")
 
 IMM_IC, IMM_LT = 0, 1
 IMM_GRAPH_LT = 0x1
+IMM_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # as include/imm.h
 STATUS = {0: "IMM_OK", 1: "IMM_EINVAL", 2: "IMM_ENOMEM", 3: "IMM_ECAPACITY", 4: "IMM_EDEVICE",
           5: "IMM_ENOTIMPL", 6: "IMM_EBUSY", 7: "IMM_ECANCELLED"}
 
@@ -34,7 +35,7 @@ EXPORTS = ("imm_init", "imm_last_error", "imm_release_cached_memory", "imm_graph
            "imm_server_submit",
            "imm_server_poll", "imm_server_wait", "imm_server_stats_get", "imm_server_destroy",
            "imm_mr_pool_create", "imm_mrim_solve", "imm_mr_lambda_prime", "imm_mr_lambda_star",
-           "imm_spread_mc")
+           "imm_spread_mc", "imm_select_seeds_noalloc", "imm_select_noalloc_bytes")
 
 
 class ImmError(RuntimeError):
@@ -133,6 +134,7 @@ def lib() -> ctypes.CDLL:
             "imm_rr_export": [p, i64, i64, p, p, i64, p],
             "imm_rr_histogram": [p, i64, i64, p],
             "imm_select_seeds": [p, i64, i64, i32, p, p, p],
+            "imm_select_seeds_noalloc": [p, i64, i64, i32, p, p, p],
             "imm_solve": [p, i32, dbl, dbl, ctypes.c_int, ctypes.POINTER(ImmOptions), p,
                           ctypes.POINTER(ImmInfo)],
             "imm_solve_pool": [p, i32, dbl, dbl, i32, p, p, ctypes.POINTER(ImmInfo)],
@@ -158,6 +160,8 @@ def lib() -> ctypes.CDLL:
             f.restype = ctypes.c_int
         L.imm_last_error.argtypes = []
         L.imm_last_error.restype = ctypes.c_char_p
+        L.imm_select_noalloc_bytes.argtypes = [p, i64, i64, i32]
+        L.imm_select_noalloc_bytes.restype = i64
         L.imm_log_binom.argtypes = [i64, i64]
         L.imm_log_binom.restype = dbl
         for name in ("imm_lambda_prime", "imm_lambda_star"):
@@ -286,6 +290,20 @@ def imm_select_seeds(p, first: int, count: int, k: int, stream=None,
     _check(lib().imm_select_seeds(p, first, count, k, _ptr(seeds), ctypes.byref(cov),
                                   _stream(stream)))
     return seeds, cov.value
+
+
+def imm_select_seeds_noalloc(p, first: int, count: int, k: int, stream=None,
+                             rounds: int = 1) -> tuple[np.ndarray, int]:
+    """imm_select_seeds with its workspace in the library's static device scratch."""
+    seeds = np.zeros(k * rounds, dtype=np.int32)
+    cov = ctypes.c_int64()
+    _check(lib().imm_select_seeds_noalloc(p, first, count, k, _ptr(seeds), ctypes.byref(cov),
+                                          _stream(stream)))
+    return seeds, cov.value
+
+
+def imm_select_noalloc_bytes(p, first: int, count: int, k: int) -> int:
+    return int(lib().imm_select_noalloc_bytes(p, first, count, k))
 
 
 def imm_solve(g, k: int, eps: float, ell: float, model: int, seed: int,

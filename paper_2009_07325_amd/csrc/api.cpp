@@ -188,7 +188,7 @@ extern "C" imm_status imm_init(int32_t device) {
     HIP_TRY(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(IMM_EINVAL, "device %d of %d", device, count);
     HIP_TRY(hipSetDevice(device));
-    return IMM_OK;
+    return noalloc_setup(device);
 }
 
 extern "C" const char* imm_last_error(void) { return g_err.c_str(); }

@@ -61,8 +61,16 @@ void drop_free(Cache& c, int device) {
 
 namespace imm {
 
+namespace {
+thread_local bool t_no_alloc = false;
+}  // namespace
+
+void set_no_alloc(bool on) { t_no_alloc = on; }
+bool no_alloc_active() { return t_no_alloc; }
+
 hipError_t dev_alloc(void** out, size_t bytes) {
     *out = nullptr;
+    if (t_no_alloc) return hipErrorOutOfMemory;
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return e;
@@ -163,6 +171,7 @@ void drop_host_free(HostCache& c) {
 
 hipError_t host_alloc(void** out, size_t bytes) {
     *out = nullptr;
+    if (t_no_alloc) return hipErrorOutOfMemory;
     int cls = kHostMinClass;
     while (cls <= kHostMaxClass && ((size_t)1 << cls) < bytes) ++cls;
     HostCache& c = host_cache();

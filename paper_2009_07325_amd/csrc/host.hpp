@@ -38,9 +38,16 @@ hipError_t dev_alloc(void** out, size_t bytes);
 void dev_free(void* p);
 size_t dev_cached_bytes();
 
+// No-allocation calls (imm_select_seeds_noalloc) set a thread-local flag for their
+// duration; every allocation attempted meanwhile fails with an error instead.
+void set_no_alloc(bool on);
+bool no_alloc_active();
+imm_status noalloc_setup(int device);
+
 template <typename T>
 imm_status dalloc(T** p, int64_t count) {
     *p = nullptr;
+    if (no_alloc_active()) return fail(IMM_ENOMEM, "device allocation inside a no-allocation call");
     if (count <= 0) count = 1;
     void* q = nullptr;
     hipError_t e = dev_alloc(&q, sizeof(T) * (size_t)count);
@@ -65,6 +72,7 @@ void host_free(void* p);
 template <typename T>
 imm_status halloc(T** p, int64_t count) {
     *p = nullptr;
+    if (no_alloc_active()) return fail(IMM_ENOMEM, "pinned host allocation inside a no-allocation call");
     if (count <= 0) count = 1;
     void* q = nullptr;
     hipError_t e = host_alloc(&q, sizeof(T) * (size_t)count);
