@@ -269,6 +269,10 @@ struct GenCtx {
     int64_t budget = 4096;              // light-wave group budget per set
     int heavy_block = 256;              // threads per heavy set (64, 128, 256 or 1024)
     int64_t heavy_scratch = (int64_t)16 << 30;   // bytes of heavy bitmaps + lists at most
+    int32_t* lt_ext = nullptr;          // LT first pass: extension lists of the grid's walk slots
+    int64_t lt_ext_words = 0;
+    int lt_lds_cap = kLtLdsCap;         // members a first-pass walk keeps in LDS / extension
+    int lt_ext_cap = kLtExtCap;
 
     LaunchCounters* lc = nullptr;
     LaunchCounters* host_lc = nullptr;  // pinned
@@ -292,7 +296,8 @@ struct GenCtx {
     int64_t heavy_launches = 0;
 
     // Defaults, then `tuning` (if given and set), then the IMM_LIGHT_BUDGET /
-    // IMM_HEAVY_BLOCK / IMM_HEAVY_SCRATCH_GIB environment overrides.
+    // IMM_HEAVY_BLOCK / IMM_HEAVY_SCRATCH_GIB / IMM_LT_LDS_CAP / IMM_LT_EXT_CAP environment
+    // overrides.
     imm_status init(int device_, imm_model model_, int cus_, const GenTuning* tuning = nullptr);
     imm_status ready();
     int64_t bytes() const;

@@ -109,7 +109,15 @@ struct GenLaunch {
     int64_t vis_words;
     int32_t* hlist;          // heavy: one member list of list_stride entries per heavy slot
     int64_t list_stride;
+    // LT first pass: members a walk keeps in LDS (at most kLtLdsCap), then in its group's
+    // extension list in HBM (lt_ext_cap entries per walk slot of the grid)
+    int32_t* lt_ext;
+    int32_t lt_lds_cap;
+    int32_t lt_ext_cap;
 };
+
+constexpr int kLtLdsCap = 256;           // LDS entries per walk of the first LT pass
+constexpr int kLtExtCap = 1024;          // extension entries per walk slot (default)
 
 constexpr uint32_t kNoHandoff = 0xFFFFFFFFu;
 constexpr int64_t kArenaWords = (int64_t)16 << 20;   // handoff arena: 64 MiB of int32
@@ -120,6 +128,7 @@ hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t 
 // otherwise the first pass (several walks per wave, guide-table steps)
 hipError_t launch_lt(const GenLaunch& a, bool big, int grid, hipStream_t s);
 int lt_walks_per_block();          // walks one block of the first LT pass runs at once
+                                   // (walk slots of a grid: grid x lt_walks_per_block())
 int rr_light_capacity();
 // Sums each instance's spread counters into out[i] and clears its n_capacity.
 hipError_t launch_pool_summary(const GenInst* inst, int32_t ninst, PoolSummary* out,

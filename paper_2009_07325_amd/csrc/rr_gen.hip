@@ -184,8 +184,10 @@ __device__ __forceinline__ void push_capacity_miss(const GenInst& I, uint32_t r)
 }
 
 // Write a finished set (members list[0..size)) into its pool; wave-cooperative.
+// Members past `split` come from `ext` (an LT walk's extension list in HBM).
 __device__ void place_wave(const GenLaunch& L, WaveState& ws, int64_t slot, int32_t inst,
-                           uint32_t r, const int32_t* list, int32_t size, uint64_t examined) {
+                           uint32_t r, const int32_t* list, int32_t size, uint64_t examined,
+                           const IMM_GLOBAL int32_t* ext = nullptr, int32_t split = 0x7FFFFFFF) {
     const int lane = lane_id();
     const GenInst& I = L.inst[inst];
     if (ws.place_inst != inst) {
@@ -209,7 +211,7 @@ __device__ void place_wave(const GenLaunch& L, WaveState& ws, int64_t slot, int3
     IMM_GLOBAL int32_t* ids = global(I.ids);
     IMM_GLOBAL uint32_t* hist = global(I.hist);
     for (int32_t i = lane; i < size; i += kWave) {
-        const int32_t v = list[i];
+        const int32_t v = i < split ? list[i] : ext[i - split];
         ids[ws.chunk_base + i] = v;
         __hip_atomic_fetch_add(hist + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -248,10 +250,6 @@ struct GraphView {
 
 __device__ __forceinline__ GraphView ic_view(const GenInst& I) {
     return GraphView{global(I.vrec), global(I.src), global(I.thr), I.k0, I.k1, I.n, I.round};
-}
-
-__device__ __forceinline__ GraphView lt_view(const GenInst& I) {
-    return GraphView{global(I.vrec), global(I.src), global(I.cum), I.k0, I.k1, I.n, I.round};
 }
 
 // Draws the in-edges of group g (edges 4g .. 4g+3) for set r; bit j of the result is set
@@ -843,62 +841,42 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
 }
 
 // ------------------------------------------------------------------------------------
-// LT: reverse walk, one wave per set.  The wave finds the chosen in-edge of the current
-// vertex: for short in-lists one coalesced load and a ballot; for long ones a 64-ary
-// search over the non-decreasing cumulative thresholds.
+// LT: reverse walks.
+//
+// A step reads its pick from the current vertex's guide table (graph.hip): one 16-byte
+// record gives the picked edge's threshold (to confirm the pick), its source, and the
+// source's in-edge range, so consecutive steps are one dependent load apart.  When a
+// threshold falls inside the draw's bucket the pick is one of the following edges of the
+// list (the last edge of a list is saturated, so the scan ends within it).
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ bool lt_hit(const GraphView& a, int64_t j, uint32_t x) {
-    const uint32_t c = a.w[j];
-    return c > x || c == kAlways;
+__device__ __forceinline__ bool lt_ok(uint32_t c, uint32_t x) { return c == kAlways || x < c; }
+
+struct LtTables {
+    const IMM_GLOBAL LtRec* grec;
+    const IMM_GLOBAL uint32_t* gidx;
+    const IMM_GLOBAL LtRec* lrec;
+};
+
+__device__ __forceinline__ LtTables lt_tables(const GenInst& I) {
+    return LtTables{global(I.grec), global(I.gidx), global(I.lrec)};
 }
 
-// First j in [s, e) whose cumulative threshold is above the draw (a saturated entry always
-// qualifies), or -1; *u is its source.  The predicate is monotone in j because cum is
-// non-decreasing within an in-list, so a 64-ary search narrows [lo, hi) by a factor of 65
-// per step.  The last probe loads each lane's source with its threshold, so the chosen
-// source needs no separate dependent load.
-__device__ __forceinline__ int64_t lt_pick(const GraphView& a, int64_t s, int64_t e, uint32_t x,
-                                           int32_t* u) {
-    const int lane = lane_id();
-    int64_t lo = s, hi = e;      // the answer lies in [lo, hi]; hi is a hit iff hi_hit
-    bool hi_hit = false;
-    while (hi - lo > kWave) {
-        const int64_t span = hi - lo;
-        const int64_t pos = lo + (span * (lane + 1)) / (kWave + 1);
-        const uint64_t m = ballot(lt_hit(a, pos, x));
-        if (m == 0) {
-            lo = (int64_t)uniform64((uint64_t)__shfl(pos, kWave - 1, kWave)) + 1;
-        } else {
-            const int f = __ffsll((unsigned long long)m) - 1;
-            const int64_t p_hit = (int64_t)uniform64((uint64_t)__shfl(pos, f, kWave));
-            const int64_t p_miss = (int64_t)uniform64((uint64_t)__shfl(pos, f > 0 ? f - 1 : 0, kWave));
-            hi = p_hit;
-            hi_hit = true;
-            if (f > 0) lo = p_miss + 1;
-        }
+// The in-edge of a vertex with in-edges [start, start + deg), deg > 0, that draw x picks.
+__device__ __forceinline__ LtRec lt_step(const LtTables& T, uint32_t start, uint32_t deg, uint32_t x) {
+    const int64_t gi = 2 * (int64_t)start + (int64_t)(((uint64_t)x * (2ull * deg)) >> 32);
+    LtRec rec = load_ltrec(T.grec + gi);
+    if (!lt_ok(rec.cum, x)) {
+        uint32_t pos = T.gidx[gi];
+        do {
+            ++pos;
+            rec = load_ltrec(T.lrec + start + pos);
+        } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
     }
-    const int64_t j = lo + lane;
-    int32_t sj = 0;
-    bool hit = false;
-    if (j < hi) {
-        sj = a.src[j];
-        hit = lt_hit(a, j, x);
-    }
-    const uint64_t m = ballot(hit);
-    if (m != 0) {
-        const int f = __ffsll((unsigned long long)m) - 1;
-        *u = __shfl(sj, f, kWave);
-        return lo + f;
-    }
-    if (hi_hit) {
-        *u = a.src[hi];
-        return hi;
-    }
-    return -1;
+    return rec;
 }
 
-// Walks too long for the on-chip list (more than kLtCap members): one walk per wave, its
-// members in an HBM list and a visited bitmap (restarted from the root).
+// Walks longer than the first pass can hold (on-chip list plus extension): one walk per
+// wave, its members in an HBM list and a visited bitmap (restarted from the root).
 __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
@@ -910,10 +888,13 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
     int32_t inst;
     uint32_t r;
     while (next_set(G, ws, inst, r)) {
-        const GraphView a = lt_view(G.inst[inst]);
-        const int32_t cap = a.n;
-        const uint32_t k0 = a.k0, k1 = a.k1;
-        int32_t v = (int32_t)root_of(r, (uint32_t)a.n, k0, k1);
+        const GenInst& I = G.inst[inst];
+        const LtTables T = lt_tables(I);
+        const int32_t cap = I.n;
+        const uint32_t k0 = I.k0, k1 = I.k1, t = I.round;
+        int32_t v = (int32_t)root_of(r, (uint32_t)I.n, k0, k1);
+        const VRec rv = load_vrec(global(I.vrec) + v);
+        uint32_t start = (uint32_t)rv.start, deg = rv.deg & kDegMask;
         if (lane == 0) {
             list[0] = v;
             vis_test_and_set(vis, v);
@@ -921,15 +902,11 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
         int32_t size = 1;
         uint64_t examined = 0;
         bool abandon = false;
-        for (;;) {
-            const VRec rec = load_vrec(a.vrec + v);
-            const uint32_t d = rec.deg & kDegMask;
-            if (d == 0) break;
-            examined += d;
-            const uint32_t x = philox10(Ctr4{r, (uint32_t)v, a.t, kDomainLT}, k0, k1).x;
-            int32_t u = 0;
-            const int64_t j = lt_pick(a, rec.start, rec.start + d, x, &u);
-            if (j < 0) break;
+        while (deg > 0) {
+            examined += deg;
+            const uint32_t x = philox10(Ctr4{r, (uint32_t)v, t, kDomainLT}, k0, k1).x;
+            const LtRec rec = lt_step(T, start, deg, x);
+            const int32_t u = rec.src;
             bool fresh = false;
             if (lane == 0) fresh = vis_test_and_set(vis, u);
             fresh = __shfl(fresh, 0, kWave);
@@ -942,6 +919,8 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
             if (lane == 0) list[size] = u;
             ++size;
             v = u;
+            start = rec.start;
+            deg = rec.deg;
         }
         __threadfence();
         if (abandon) push_heavy(G, ws, inst, r);
@@ -955,28 +934,29 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
 
 // ------------------------------------------------------------------------------------
 // LT: the first pass of every launch.  A group of kLtGroup lanes runs one walk (kLtWalks
-// walks per wave), its members in an LDS list that is also its revisit test: the group's
-// lanes compare the picked vertex with the list, kLtGroup entries per step of the scan.
-// A step reads the pick from v's guide table (graph.hip): one 16-byte record gives the
-// picked edge's threshold (to confirm the pick), its source, and the source's in-edge
-// range, so consecutive steps are one dependent load apart.  The group's lanes compute
-// the same values (its draw, its loads, broadcast to the group); the wave places finished
-// walks one at a time.  Walks longer than kLtCap members are redrawn by k_rr_lt_hbm.
+// walks per wave), its first G.lt_lds_cap members in an LDS list and the next
+// G.lt_ext_cap in the group's extension list in HBM; together they are the walk's revisit
+// test (the group's lanes compare the picked vertex with the lists, kLtGroup entries per
+// step of the scan).  Walks on RR sets are short (on R-MAT scale 22 the median is one
+// member and the 99.99th percentile ~500), so the extension is rarely touched; it lets the
+// few long walks finish here instead of being redrawn.  The group's lanes compute the same
+// values (its draw, its loads, broadcast to the group); the wave places finished walks one
+// at a time.  Walks longer than both lists are redrawn by k_rr_lt_hbm.
 // ------------------------------------------------------------------------------------
 constexpr int kLtGroup = 16;
 constexpr int kLtWalks = kWave / kLtGroup;
-constexpr int kLtCap = 512;
-
-__device__ __forceinline__ bool lt_ok(uint32_t c, uint32_t x) { return c == kAlways || x < c; }
 
 __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
-    __shared__ int32_t lists[kWavesPerBlock][kLtWalks][kLtCap];
+    __shared__ int32_t lists[kWavesPerBlock][kLtWalks][kLtLdsCap];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     const int grp = lane / kLtGroup, gl = lane % kLtGroup;
     const uint64_t gmask = 0xFFFFull << (grp * kLtGroup);
     int32_t* list = lists[wib][grp];
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
+    const int32_t lcap = G.lt_lds_cap, ecap = G.lt_ext_cap;
+    IMM_GLOBAL int32_t* ext_wave = global(G.lt_ext) + slot * kLtWalks * (int64_t)ecap;
+    IMM_GLOBAL int32_t* ext = ext_wave + grp * (int64_t)ecap;
     WaveState ws;
 
     // the group's walk (the same values in each of its lanes)
@@ -984,9 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
     int32_t inst = 0, v = 0, size = 0;
     uint32_t r = 0, start = 0, deg = 0, k0 = 0, k1 = 0, t = 0;
     uint64_t examined = 0;
-    const IMM_GLOBAL LtRec* grec = nullptr;
-    const IMM_GLOBAL uint32_t* gidx = nullptr;
-    const IMM_GLOBAL LtRec* lrec = nullptr;
+    LtTables T{nullptr, nullptr, nullptr};
     bool more = true;                      // the launch still has RR indices (uniform)
 
     for (;;) {
@@ -1005,9 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
                 const GenInst& I = G.inst[wi];
                 inst = wi;
                 r = wr;
-                grec = global(I.grec);
-                gidx = global(I.gidx);
-                lrec = global(I.lrec);
+                T = lt_tables(I);
                 k0 = I.k0;
                 k1 = I.k1;
                 t = I.round;
@@ -1031,31 +1007,28 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
             } else {
                 examined += deg;
                 const uint32_t x = philox10(Ctr4{r, (uint32_t)v, t, kDomainLT}, k0, k1).x;
-                const int64_t gi = 2 * (int64_t)start + (int64_t)(((uint64_t)x * (2ull * deg)) >> 32);
-                LtRec rec = load_ltrec(grec + gi);
-                if (!lt_ok(rec.cum, x)) {
-                    // a threshold inside the bucket: the pick is one of the next edges
-                    // (the last edge of a list is saturated, so the scan ends within it)
-                    uint32_t pos = gidx[gi];
-                    do {
-                        ++pos;
-                        rec = load_ltrec(lrec + start + pos);
-                    } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
-                }
+                const LtRec rec = lt_step(T, start, deg, x);
                 const int32_t u = rec.src;
                 bool hit = false;
-                for (int32_t i = gl; i < size; i += kLtGroup) hit |= list[i] == u;
+                const int32_t in_lds = min(size, lcap);
+                for (int32_t i = gl; i < in_lds; i += kLtGroup) hit |= list[i] == u;
+                for (int32_t i = gl; i < size - lcap; i += kLtGroup) hit |= ext[i] == u;
                 if ((ballot(hit) & gmask) != 0) {
                     done = true;                    // u is already on the walk
-                } else if (size >= kLtCap) {
+                } else if (size >= lcap + ecap) {
                     done = true;
                     abandon = true;
                 } else {
-                    if (gl == 0) list[size] = u;
+                    if (gl == 0) {
+                        if (size < lcap) list[size] = u;
+                        else ext[size - lcap] = u;
+                    }
                     ++size;
                     v = u;
                     start = rec.start;
                     deg = rec.deg;
+                    // the group's later scans read the extension entry written above
+                    if (size > lcap) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 }
             }
         }
@@ -1071,7 +1044,8 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
             const uint64_t fe = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(examined >> 32), b) << 32) |
                                 __builtin_amdgcn_readlane((uint32_t)examined, b);
             if (__builtin_amdgcn_readlane((int)abandon, b)) push_heavy(G, ws, fi, fr);
-            else place_wave(G, ws, slot, fi, fr, lists[wib][b / kLtGroup], fs, fe);
+            else place_wave(G, ws, slot, fi, fr, lists[wib][b / kLtGroup], fs, fe,
+                            ext_wave + (b / kLtGroup) * (int64_t)ecap, lcap);
         }
         if (done) active = false;
         wave_sync();
@@ -1079,9 +1053,6 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
     wave_exit(G, ws, slot);
 }
 
-// ------------------------------------------------------------------------------------
-// launchers
-// ------------------------------------------------------------------------------------
 hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s) {
     k_ic_light<<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();

@@ -183,6 +183,21 @@ def test_rr_sets_lt_long_walks(imm_gpu):
     _compare_pool(imm_gpu, g, imm_gpu.IMM_LT, 1234, 3000, lt_w=w)
 
 
+@pytest.mark.parametrize("lds_cap,ext_cap", [(4, 16), (1, 0), (32, 1)])
+def test_rr_sets_lt_extension_lists(imm_gpu, monkeypatch, lds_cap, ext_cap):
+    """First-pass walks past the LDS list continue in the group's extension list in HBM,
+    and walks past both are redrawn by the HBM-list kernel; small list capacities force
+    both paths on ordinary walks (the defaults hold 256 + 1024 members)."""
+    monkeypatch.setenv("IMM_LT_LDS_CAP", str(lds_cap))
+    monkeypatch.setenv("IMM_LT_EXT_CAP", str(ext_cap))
+    g = graphs.rmat(14, 16 << 14, seed=61)
+    w = graphs.lt_uniform_weights(g, seed=62)
+    _, ref = _compare_pool(imm_gpu, g, imm_gpu.IMM_LT, 0x5EED0013, 20_000, lt_w=w,
+                           chunks=[3, 20_000])
+    sizes = np.diff(ref.export()[0])
+    assert (sizes > lds_cap).sum() > 100 and (sizes > lds_cap + ext_cap).sum() > 10
+
+
 @pytest.mark.parametrize("first,count,k", [(0, 5000, 10), (1000, 3000, 25), (0, 5000, 1000)])
 def test_select_matches_oracle(imm_gpu, first, count, k):
     w = configs.c1()
