@@ -201,6 +201,7 @@ struct SelInst {
     const int64_t* seg_off[kMaxSegs];
     const uint32_t* seg_inv[kMaxSegs];
 };
+constexpr int kMaxCoopGrid = 1024;   // blocks of a cooperative selection launch at most
 // Arrival counters of a hierarchical grid barrier (zeroed before each launch): block b
 // arrives on sub[b % 16]; the last arrival of a group bumps top; all wait for top.
 struct alignas(64) GridBarrier {
@@ -208,6 +209,7 @@ struct alignas(64) GridBarrier {
     unsigned int top;
     unsigned int err;              // set when a barrier wait timed out
     unsigned int pad[14];
+    unsigned long long bkeys[kMaxCoopGrid];  // single-instance selection: each block's argmax key
 };
 int select_coop_grid();            // blocks of the cooperative launch (co-resident)
 int select_max_inst();             // instances one cooperative launch can take

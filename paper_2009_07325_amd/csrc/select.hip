@@ -227,8 +227,8 @@ hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStre
 // ---- greedy rounds ------------------------------------------------------------------
 // key(v) = (h[v] + 1) << 32 | (2^32 - 1 - v): the largest key has the largest count and,
 // among equal counts, the smallest id.  Chosen vertices hold h = -1 (key high part 0), so
-// any vertex not chosen beats them; the vertex chosen in round j - 1 is set to -1 by the
-// argmax of round j, after its cover step has finished.
+// any vertex not chosen beats them; the vertex chosen in a round is set to -1 in that
+// round's cover step, which never decrements it.
 // ---- all rounds in one cooperative launch ---------------------------------------------
 constexpr int kCoopBlock = 1024;
 constexpr int kCoopWaves = kCoopBlock / kWave;
@@ -291,14 +291,6 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* bar, unsigned int& epoch)
     __syncthreads();
     return s_ok != 0;
 }
-
-// Per-wave staging of one cover batch: exclusive prefix of the newly covered sets' sizes
-// and, per set, its members and its instance's counters.
-struct CoverLds {
-    int32_t pre[kWave + 1];
-    int32_t inst[kWave];
-    const int32_t* mem[kWave];
-};
 
 // Per-block combining of counter decrements.  In the first rounds the newly covered sets
 // overlap heavily, so the same counters are decremented from many blocks; device-scope
@@ -377,15 +369,32 @@ __device__ __forceinline__ void block_key_max(unsigned long long best,
     __syncthreads();
 }
 
+// Block-wide maximum of every thread's key, stored (0 when the block saw no candidate) at
+// *slot.  Called by all threads of the block.
+__device__ __forceinline__ void block_key_store(unsigned long long best, unsigned long long* slot,
+                                                unsigned long long* red, int lane, int wid, int tid) {
+    best = wave_max_u64(best);
+    if (lane == 0) red[wid] = best;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kCoopWaves; ++w) best = red[w] > best ? red[w] : best;
+        st_co(slot, best);
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __restrict__ inst,
                                                             int32_t ninst, int32_t maxk,
                                                             GridBarrier* bar) {
     __shared__ int64_t tile_pre[kMaxInst + 1];    // argmax tiles per instance, prefix
     __shared__ int64_t ent_pre[kMaxInst + 1];     // cover entries per instance, prefix
     __shared__ int64_t ent_beg[kMaxInst];
+    __shared__ int32_t chosen[kMaxInst];          // each instance's vertex of this round
     __shared__ unsigned long long red[kCoopWaves];
     __shared__ int64_t wsum[kCoopWaves];
-    __shared__ CoverLds cov_all[kCoopWaves];
+    __shared__ int64_t set_pre[kCoopBlock + 1];   // cover batch: prefix of new sets' sizes
+    __shared__ const int32_t* set_mem[kCoopBlock];
+    __shared__ int32_t set_inst[kCoopBlock];
     __shared__ DecCache dc;
     __shared__ unsigned char stopped[kMaxInst];   // estimation phase decided (failed)
     __shared__ int64_t seg_pre[kMaxSegs + 1];     // single instance: its entries per segment
@@ -396,6 +405,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     }
     if (threadIdx.x < kMaxInst) stopped[threadIdx.x] = 0;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const bool solo = ninst == 1;
     unsigned int epoch = 0;
     // instance prefixes are computed one instance per thread (kMaxInst == kCoopBlock); the
     // tables past ninst repeat the total
@@ -407,8 +417,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         // thread i keeps instance i's
         const int64_t cov_before = tid < ninst ? (int64_t)ld_co(global(inst[tid].n_covered)) : 0;
         // ---- argmax: tiles of kArgTile counters, any instance still selecting ----
-        // A block's successive tiles of one instance share one block reduction and one
-        // atomic (tiles are grouped by instance, so an instance's tiles are consecutive).
+        // A block's successive tiles of one instance share one block reduction (tiles are
+        // grouped by instance, so an instance's tiles are consecutive).  A single-instance
+        // launch leaves each block's maximum in bar->bkeys (reduced after the barrier);
+        // several instances merge theirs into the instance's key with an atomic.
         unsigned long long best = 0;
         int cur = -1;                                    // instance of `best`, block-uniform
         for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -424,7 +436,6 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 cur = lo;
                 best = 0;
             }
-            const int32_t prev = round > 0 ? ld_co(global(I.seeds) + round - 1) : -1;
             // partition matroid: the parts that already hold part_k chosen elements
             uint64_t full = 0;
             if (I.part_n > 0) {
@@ -432,7 +443,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 const int32_t tk = lane < parts ? ld_co(global(I.taken) + lane) : 0;
                 full = ballot(lane < parts && tk >= I.part_k);
             }
-            IMM_GLOBAL int32_t* h = global(I.h);
+            const IMM_GLOBAL int32_t* h = global(I.h);
             // up to kArgGroup of the block's successive tiles of this instance are loaded
             // together
             const int64_t left = (tile_pre[lo + 1] - t + gridDim.x - 1) / gridDim.x;
@@ -448,10 +459,6 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
 #pragma unroll
             for (int j = 0; j < 4 * kArgGroup; ++j) {
                 const int64_t v = base + (j >> 2) * step + (j & 3) * kCoopBlock + tid;
-                if (c[j] >= 0 && (int32_t)v == prev) {
-                    st_co(h + v, -1);
-                    c[j] = -1;
-                }
                 if (full != 0 && c[j] >= 0 && ((full >> ((uint32_t)v / (uint32_t)I.part_n)) & 1ull))
                     c[j] = -1;
                 if (c[j] >= 0) {
@@ -462,16 +469,29 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             }
             t += (int64_t)(m - 1) * gridDim.x;
         }
-        if (cur >= 0) block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
+        if (solo) {
+            block_key_store(best, bar->bkeys + blockIdx.x, red, lane, wid, tid);
+        } else if (cur >= 0) {
+            block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
+        }
         if (!grid_sync(bar, epoch)) return;
         // ---- cover: sets containing each instance's new seed ----
         // Every block reads the same final keys and coverage, so every block takes the same
         // stop decisions.
+        unsigned long long solo_key = 0;
+        if (solo && wid == 0) {
+            unsigned long long k = 0;
+            for (int b = lane; b < (int)gridDim.x; b += kWave) {
+                const unsigned long long x = ld_co(bar->bkeys + b);
+                k = x > k ? x : k;
+            }
+            solo_key = wave_max_u64(k);
+        }
         int64_t cnt = 0;
         bool live = false;
         if (tid < ninst && round < inst[tid].k && !stopped[tid]) {
             const SelInst& I = inst[tid];
-            const unsigned long long key = ld_co(global(I.keys) + round);
+            const unsigned long long key = solo ? solo_key : ld_co(global(I.keys) + round);
             const int64_t gain = key ? (int64_t)(key >> 32) - 1 : 0;
             const int64_t bound = cov_before + (int64_t)(I.k - round) * gain;
             if (I.need > 0 && bound < I.need) {
@@ -479,6 +499,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             } else {
                 live = true;
                 const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
+                chosen[tid] = u;
                 if (I.nseg > 1) {              // only in single-instance launches
                     int64_t acc = 0;
                     for (int j = 0; j < I.nseg; ++j) {
@@ -496,7 +517,11 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                     cnt = global(I.inv_off)[u + 1] - beg;
                 }
                 if (blockIdx.x == 0) {
+                    // u leaves the candidates now: its own counter is never decremented
+                    // (every set holding it is covered in this round, and the cover step
+                    // skips it), so the next argmax sees -1
                     st_co(global(I.seeds) + round, u);
+                    st_co(global(I.h) + u, -1);
                     if (I.part_n > 0) atomic_add_agent(global(I.taken) + u / I.part_n, 1);
                 }
             }
@@ -504,25 +529,22 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         if (!__syncthreads_or(live)) return;            // every instance finished or stopped
         block_excl_scan_i64(cnt, ent_pre, wsum);
         const int64_t nent = ent_pre[ninst];
-        // A wave takes `per` consecutive entries at a time (one per lane, per = 1..64, the
-        // largest power of two that still gives every wave work): those lanes test and mark
-        // their sets' covered flags together, then the members of the newly covered sets
-        // are flattened over the wave (prefix of set sizes in LDS) and decremented four per
-        // lane at a time, so the memory latencies of a batch overlap.
-        CoverLds& C = cov_all[wid];
-        const int64_t gwave = (int64_t)blockIdx.x * kCoopWaves + wid;
-        const int64_t nwaves = (int64_t)gridDim.x * kCoopWaves;
-        const int64_t ratio = nent / nwaves;
-        const int per = ratio >= 64 ? 64 : ratio >= 1 ? (1 << (63 - __builtin_clzll((unsigned long long)ratio))) : 1;
+        // Block b takes entries [nent b / G, nent (b+1) / G) in batches of one per thread:
+        // each thread tests and marks its entry's set; the sizes of the batch's newly covered
+        // sets are scanned over the block, and the block's waves then share the flattened
+        // members (consecutive lanes on consecutive members of a set, four per lane in
+        // flight), each member found by a binary search over the batch's prefix.
+        const int64_t e_lo = nent * (int64_t)blockIdx.x / gridDim.x;
+        const int64_t e_hi = nent * ((int64_t)blockIdx.x + 1) / gridDim.x;
         unsigned long long mine = 0;
         int mine_inst = -1;
-        for (int64_t e0 = gwave * per; e0 < nent; e0 += nwaves * per) {
-            const int64_t e = e0 + lane;
+        for (int64_t eb = e_lo; eb < e_hi; eb += kCoopBlock) {
+            const int64_t e = eb + tid;
             int li = -1;
             bool fresh = false;
-            int32_t len = 0;
+            int64_t len = 0;
             const int32_t* mem = nullptr;
-            if (lane < per && e < nent) {
+            if (e < e_hi) {
                 int lo = 0, hi = ninst;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
@@ -559,35 +581,32 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 mine += (unsigned long long)__popcll(mx);
                 pending &= ~mx;
             }
-            const int32_t incl = wave_incl_scan(len);
-            const int32_t total = __shfl(incl, kWave - 1, kWave);
-            if (total == 0) continue;
-            C.pre[lane] = incl - len;
-            C.mem[lane] = mem;
-            C.inst[lane] = li;
-            if (lane == kWave - 1) C.pre[kWave] = incl;
-            wave_sync();
-            for (int32_t q0 = 0; q0 < total; q0 += 4 * kWave) {
+            block_excl_scan_i64(len, set_pre, wsum);
+            set_mem[tid] = mem;
+            set_inst[tid] = li;
+            __syncthreads();
+            const int64_t total = set_pre[kCoopBlock];
+            for (int64_t q0 = (int64_t)wid * (4 * kWave); q0 < total; q0 += 4 * kCoopBlock) {
                 int32_t v[4], vi[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int32_t q = q0 + u * kWave + lane;
+                    const int64_t q = q0 + u * kWave + lane;
                     vi[u] = -1;
                     if (q < total) {
-                        int lo = 0, hi = per;     // pre[lo] <= q < pre[lo] + len[lo]
+                        int lo = 0, hi = kCoopBlock;   // set_pre[lo] <= q < set_pre[lo + 1]
                         while (hi - lo > 1) {
                             const int mid = (lo + hi) >> 1;
-                            if (C.pre[mid] <= q) lo = mid; else hi = mid;
+                            if (set_pre[mid] <= q) lo = mid; else hi = mid;
                         }
-                        v[u] = global(C.mem[lo])[q - C.pre[lo]];
-                        vi[u] = C.inst[lo];
+                        v[u] = global(set_mem[lo])[q - set_pre[lo]];
+                        vi[u] = set_inst[lo];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (vi[u] >= 0) dec_counter(dc, inst, vi[u], v[u]);
+                    if (vi[u] >= 0 && v[u] != chosen[vi[u]]) dec_counter(dc, inst, vi[u], v[u]);
             }
-            wave_sync();
+            __syncthreads();                    // the batch tables are rewritten next
         }
         if (mine && lane == 0) atomic_add_agent(global(inst[mine_inst].n_covered), mine);
         dec_flush(dc, inst);
@@ -637,6 +656,7 @@ hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, 
     const int grid = select_coop_grid();
     const int capacity = select_coop_capacity();
     if (capacity < 1 || grid > capacity) return hipErrorCooperativeLaunchTooLarge;
+    if (grid > kMaxCoopGrid) return hipErrorInvalidValue;
     if (plain_launch()) {
         k_select_coop<<<grid, kCoopBlock, 0, s>>>(inst, ninst, maxk, bar);
         return hipGetLastError();
