@@ -942,6 +942,14 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
 // few long walks finish here instead of being redrawn.  The group's lanes compute the same
 // values (its draw, its loads, broadcast to the group); the wave places finished walks one
 // at a time.  Walks longer than both lists are redrawn by k_rr_lt_hbm.
+//
+// Each step is one dependent load, so the kernel is organised to keep that load in flight
+// while the wave does everything else: when a walk's pick u arrives, the draw and guide
+// load of u's own step are issued at once, before u is tested against the walk (a revisit
+// ends the walk once, so the speculation is almost always right; a wrong one costs one
+// unused load), and the revisit scans, placements of finished walks and starts of new
+// walks of the wave all run while those loads travel.  A new walk's root record is
+// likewise loaded one iteration before its first draw.
 // ------------------------------------------------------------------------------------
 constexpr int kLtGroup = 16;
 constexpr int kLtWalks = kWave / kLtGroup;
@@ -959,16 +967,107 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
     IMM_GLOBAL int32_t* ext = ext_wave + grp * (int64_t)ecap;
     WaveState ws;
 
-    // the group's walk (the same values in each of its lanes)
+    // the group's walk (the same values in each of its lanes).  phase 0: the root's vertex
+    // record `vr` is in flight; phase 1: the pick `rec` of the current vertex v (in-edges
+    // [start, start + deg), draw x, guide entry gi) is in flight.
     bool active = false;
+    int phase = 0;
     int32_t inst = 0, v = 0, size = 0;
-    uint32_t r = 0, start = 0, deg = 0, k0 = 0, k1 = 0, t = 0;
+    uint32_t r = 0, start = 0, deg = 0, x = 0, k0 = 0, k1 = 0, t = 0;
+    int64_t gi = 0;
     uint64_t examined = 0;
+    VRec vr{};
+    LtRec rec{};
     LtTables T{nullptr, nullptr, nullptr};
     bool more = true;                      // the launch still has RR indices (uniform)
 
     for (;;) {
-        // idle groups take the launch's next RR indices, one each
+        // ---- one step of every walk whose load was issued in an earlier iteration ----
+        bool done = false, abandon = false;
+        if (active) {
+            if (phase == 0) {
+                start = (uint32_t)vr.start;
+                deg = vr.deg & kDegMask;
+                if (deg == 0) {
+                    done = true;                        // the root has no in-edge
+                } else {
+                    examined += deg;
+                    x = philox10(Ctr4{r, (uint32_t)v, t, kDomainLT}, k0, k1).x;
+                    gi = 2 * (int64_t)start + (int64_t)(((uint64_t)x * (2ull * deg)) >> 32);
+                    rec = load_ltrec(T.grec + gi);
+                    phase = 1;
+                }
+            } else {
+                if (!lt_ok(rec.cum, x)) {
+                    // a threshold inside the draw's bucket: the pick is one of the next
+                    // edges (the list's last edge is saturated, so the scan ends within it)
+                    uint32_t pos = T.gidx[gi];
+                    do {
+                        ++pos;
+                        rec = load_ltrec(T.lrec + start + pos);
+                    } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
+                }
+                const int32_t u = rec.src;
+                const uint32_t ustart = rec.start, udeg = rec.deg;
+                // u's own step, issued before u is known to be new
+                uint32_t ux = 0;
+                int64_t ugi = 0;
+                LtRec urec{};
+                if (udeg > 0) {
+                    ux = philox10(Ctr4{r, (uint32_t)u, t, kDomainLT}, k0, k1).x;
+                    ugi = 2 * (int64_t)ustart + (int64_t)(((uint64_t)ux * (2ull * udeg)) >> 32);
+                    urec = load_ltrec(T.grec + ugi);
+                }
+                bool hit = false;
+                const int32_t in_lds = min(size, lcap);
+                for (int32_t i = gl; i < in_lds; i += kLtGroup) hit |= list[i] == u;
+                for (int32_t i = gl; i < size - lcap; i += kLtGroup) hit |= ext[i] == u;
+                if ((ballot(hit) & gmask) != 0) {
+                    done = true;                        // u is already on the walk
+                } else if (size >= lcap + ecap) {
+                    done = true;
+                    abandon = true;
+                } else {
+                    if (gl == 0) {
+                        if (size < lcap) list[size] = u;
+                        else ext[size - lcap] = u;
+                    }
+                    ++size;
+                    // the group's later scans read the extension entry written above
+                    if (size > lcap) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    if (udeg == 0) {
+                        done = true;                    // u has no in-edge
+                    } else {
+                        examined += udeg;
+                        v = u;
+                        start = ustart;
+                        deg = udeg;
+                        x = ux;
+                        gi = ugi;
+                        rec = urec;
+                    }
+                }
+            }
+        }
+        wave_sync();
+        // ---- finished walks, one group at a time ----
+        uint64_t fin = ballot(done && gl == 0);
+        while (fin) {
+            const int b = __ffsll((unsigned long long)fin) - 1;
+            fin &= fin - 1;
+            const int32_t fi = __builtin_amdgcn_readlane(inst, b);
+            const uint32_t fr = __builtin_amdgcn_readlane(r, b);
+            const int32_t fs = __builtin_amdgcn_readlane(size, b);
+            const uint64_t fe = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(examined >> 32), b) << 32) |
+                                __builtin_amdgcn_readlane((uint32_t)examined, b);
+            if (__builtin_amdgcn_readlane((int)abandon, b)) push_heavy(G, ws, fi, fr);
+            else place_wave(G, ws, slot, fi, fr, lists[wib][b / kLtGroup], fs, fe,
+                            ext_wave + (b / kLtGroup) * (int64_t)ecap, lcap);
+        }
+        if (done) active = false;
+        wave_sync();
+        // ---- idle groups start the launch's next walks: the root's record is loaded now
+        // and read in the next iteration ----
         uint64_t idle = ballot(!active && gl == 0);
         while (idle && more) {
             int32_t wi;
@@ -988,66 +1087,15 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
                 k1 = I.k1;
                 t = I.round;
                 v = (int32_t)root_of(r, (uint32_t)I.n, k0, k1);
-                const VRec rec = load_vrec(global(I.vrec) + v);
-                start = (uint32_t)rec.start;
-                deg = rec.deg & kDegMask;
+                vr = load_vrec(global(I.vrec) + v);
                 if (gl == 0) list[0] = v;
                 size = 1;
                 examined = 0;
+                phase = 0;
                 active = true;
             }
         }
         if (ballot(active) == 0) break;     // no walk left and no index left
-        wave_sync();
-        // one step of every walk
-        bool done = false, abandon = false;
-        if (active) {
-            if (deg == 0) {
-                done = true;
-            } else {
-                examined += deg;
-                const uint32_t x = philox10(Ctr4{r, (uint32_t)v, t, kDomainLT}, k0, k1).x;
-                const LtRec rec = lt_step(T, start, deg, x);
-                const int32_t u = rec.src;
-                bool hit = false;
-                const int32_t in_lds = min(size, lcap);
-                for (int32_t i = gl; i < in_lds; i += kLtGroup) hit |= list[i] == u;
-                for (int32_t i = gl; i < size - lcap; i += kLtGroup) hit |= ext[i] == u;
-                if ((ballot(hit) & gmask) != 0) {
-                    done = true;                    // u is already on the walk
-                } else if (size >= lcap + ecap) {
-                    done = true;
-                    abandon = true;
-                } else {
-                    if (gl == 0) {
-                        if (size < lcap) list[size] = u;
-                        else ext[size - lcap] = u;
-                    }
-                    ++size;
-                    v = u;
-                    start = rec.start;
-                    deg = rec.deg;
-                    // the group's later scans read the extension entry written above
-                    if (size > lcap) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                }
-            }
-        }
-        wave_sync();
-        // finished walks, one group at a time
-        uint64_t fin = ballot(done && gl == 0);
-        while (fin) {
-            const int b = __ffsll((unsigned long long)fin) - 1;
-            fin &= fin - 1;
-            const int32_t fi = __builtin_amdgcn_readlane(inst, b);
-            const uint32_t fr = __builtin_amdgcn_readlane(r, b);
-            const int32_t fs = __builtin_amdgcn_readlane(size, b);
-            const uint64_t fe = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(examined >> 32), b) << 32) |
-                                __builtin_amdgcn_readlane((uint32_t)examined, b);
-            if (__builtin_amdgcn_readlane((int)abandon, b)) push_heavy(G, ws, fi, fr);
-            else place_wave(G, ws, slot, fi, fr, lists[wib][b / kLtGroup], fs, fe,
-                            ext_wave + (b / kLtGroup) * (int64_t)ecap, lcap);
-        }
-        if (done) active = false;
         wave_sync();
     }
     wave_exit(G, ws, slot);
