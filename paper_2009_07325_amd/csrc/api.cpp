@@ -490,7 +490,7 @@ extern "C" imm_status imm_rr_histogram(const imm_pool* pc, int64_t first, int64_
 // selection
 // ------------------------------------------------------------------------------------
 int64_t SelectWs::bytes() const {
-    int64_t b = 0;
+    int64_t b = (hot_bits ? (n + 31) / 32 * 4 + kSelectHotBuckets * 4 + 8 : 0) + hot_cap * 4;
     if (h) b += n * (4 + 4 + 8 + 4) + 8;
     for (const IndexSeg& x : seg) b += x.off ? (n + 1) * 8 + x.cap * 4 : 0;
     if (snap) b += n * 4;
@@ -519,7 +519,11 @@ void SelectWs::release() {
     dfree(n_covered);
     hfree(host_seeds);
     hfree(host_cov);
-    cap_cov = cap_k = 0;
+    dfree(hot_bits);
+    dfree(cnt_hist);
+    dfree(hot_n);
+    dfree(hot_ids);
+    cap_cov = cap_k = hot_cap = 0;
 }
 
 void SelectLaunch::release() {
@@ -585,14 +589,39 @@ static imm_status index_segment(imm_pool* p, SelectWs* w, const uint32_t* cnt, i
     return IMM_OK;
 }
 
+int32_t imm::select_hot_max(int64_t n) {
+    int64_t t = 16384;
+    bool forced = false;
+    if (const char* e = getenv("IMM_SELECT_HOT")) {
+        t = std::max(0ll, atoll(e));
+        forced = true;
+    }
+    t = std::min<int64_t>(t, (int64_t)kSelectHotPerBlock * select_coop_grid());
+    if (t <= 0 || n <= (forced ? t : 2 * t)) return 0;
+    return (int32_t)t;
+}
+
 imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t kr,
-                               hipStream_t s, SelInst* out, bool segments) {
+                               hipStream_t s, SelInst* out, bool segments, bool hot) {
     const int32_t n = p->g->n;
     const int32_t k = kr * p->rounds;        // multi-round: kr seeds per round
     IMM_TRY(ensure_select(p, w, count, k));
+    const int32_t hot_max = hot ? select_hot_max(n) : 0;
+    if (hot_max > 0) {
+        if (!w->hot_bits) {
+            IMM_TRY(dalloc(&w->hot_bits, (n + 31) / 32));
+            IMM_TRY(dalloc(&w->cnt_hist, kSelectHotBuckets));
+            IMM_TRY(dalloc(&w->hot_n, 2));
+        }
+        if (hot_max > w->hot_cap) {
+            dfree(w->hot_ids);
+            IMM_TRY(dalloc(&w->hot_ids, hot_max));
+            w->hot_cap = hot_max;
+        }
+    }
     const uint32_t* hsrc = nullptr;
     IMM_TRY(range_hist(p, w, first, count, &hsrc, s));
-    HIP_TRY(launch_copy_hist(hsrc, w->h, n, s));
+    if (hot_max == 0) HIP_TRY(launch_copy_hist(hsrc, w->h, n, s));
     const bool prefix = first == 0 && count == p->count;      // hsrc is the pool histogram
     const int64_t placed = (int64_t)p->sum.placed;
     if (segments && prefix && w->ix_pool == p && w->snap_valid && w->ix_first == 0 &&
@@ -623,6 +652,13 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
         }
     }
     HIP_TRY(launch_fill_u32(w->covered, count, 0u, s));
+    if (hot_max > 0) {
+        HIP_TRY(launch_fill_u32(w->hot_bits, (n + 31) / 32, 0u, s));
+        HIP_TRY(launch_fill_u32(w->cnt_hist, kSelectHotBuckets, 0u, s));
+        HIP_TRY(launch_fill_u32(w->hot_n, 2, 0u, s));
+        HIP_TRY(launch_hot_prepare(hsrc, w->h, n, hot_max, w->cnt_hist, w->hot_bits, w->hot_ids,
+                                   w->hot_n, s));
+    }
     HIP_TRY(launch_fill_u64(w->keys, k, 0ull, s));
     HIP_TRY(launch_fill_u64(w->n_covered, 1, 0ull, s));
     if (p->rounds > 1) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(w->taken), kMaxRounds, 0u, s));
@@ -650,6 +686,11 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
     si.keys = w->keys;
     si.seeds = w->seeds;
     si.n_covered = w->n_covered;
+    si.h0 = hsrc;
+    si.hot_max = hot_max;
+    si.hot_bits = w->hot_bits;
+    si.hot_n = w->hot_n;
+    si.hot_ids = w->hot_ids;
     *out = si;
     return IMM_OK;
 }
@@ -692,7 +733,7 @@ static imm_status pool_select(imm_pool* p, int64_t first, int64_t count, int32_t
                               int32_t* seeds_out, int64_t* covered_out, hipStream_t s,
                               int64_t need = 0) {
     SelInst si;
-    IMM_TRY(select_prepare(p, &p->sel, first, count, k, s, &si, true));
+    IMM_TRY(select_prepare(p, &p->sel, first, count, k, s, &si, true, true));
     si.need = need;
     SelectWs* w = &p->sel;
     IMM_TRY(select_run(&p->launch, &w, &si, 1, s));

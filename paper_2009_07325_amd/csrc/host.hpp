@@ -238,6 +238,12 @@ struct SelectWs {
     int32_t* host_seeds = nullptr;            // pinned, cap_k
     unsigned long long* host_cov = nullptr;   // pinned
     int32_t k = 0;                            // of the prepared selection
+    // hot set of single-instance selections (select.hip)
+    uint32_t* hot_bits = nullptr;             // n bits
+    uint32_t* cnt_hist = nullptr;             // kSelectHotBuckets
+    uint32_t* hot_n = nullptr;
+    int32_t* hot_ids = nullptr;               // hot_cap
+    int64_t hot_cap = 0;
 
     int64_t bytes() const;
     void release();
@@ -365,8 +371,13 @@ imm_status check_range(const imm_pool* p, int64_t first, int64_t count);
 // Launches the per-selection setup kernels (counts, inverted index, clears) on `s` and
 // fills `out` with the instance descriptor.
 // segments: the index may be kept as segments across calls (single-instance launches only)
+// hot: the selection runs alone in its launch and may keep a hot set (select.hip)
 imm_status select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count, int32_t k,
-                          hipStream_t s, SelInst* out, bool segments = false);
+                          hipStream_t s, SelInst* out, bool segments = false, bool hot = false);
+// Hot-set size of a single-instance selection over n counters (0: off).  16384 by default
+// (IMM_SELECT_HOT overrides; 0 turns it off), used only when n exceeds twice that (or the
+// override), and at most kSelectHotPerBlock per block of the launch.
+int32_t select_hot_max(int64_t n);
 // Runs all rounds of every prepared instance in one cooperative launch, then copies each
 // instance's seeds and covered count to its workspace's pinned buffers (synchronises s).
 imm_status select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,

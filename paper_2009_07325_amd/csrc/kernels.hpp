@@ -159,6 +159,12 @@ hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, co
 // out[v] = a[v] - b[v]
 hipError_t launch_sub_u32(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStream_t s);
+// Hot set of a single-instance selection: h = hist (as launch_copy_hist), the histogram of
+// the counts into cnt_hist (kSelectHotBuckets, zeroed), then the threshold and the hot list
+// into hot_bits (n bits, zeroed), hot_ids (hot_max) and hot_n (2 words, zeroed).
+hipError_t launch_hot_prepare(const uint32_t* hist, int32_t* h, int64_t n, int32_t hot_max,
+                              uint32_t* cnt_hist, uint32_t* hot_bits, int32_t* hot_ids,
+                              uint32_t* hot_n, hipStream_t s);
 // All k rounds of greedy selection for one or more instances in one cooperative launch:
 // per round a segmented argmax over every instance's counters, a grid barrier, the cover
 // step of every instance, a grid barrier.
@@ -200,7 +206,18 @@ struct SelInst {
     int32_t* taken;                // per part (at most kMaxRounds), zeroed
     const int64_t* seg_off[kMaxSegs];
     const uint32_t* seg_inv[kMaxSegs];
+    // Single-instance launches: hot set of at most hot_max vertices (0: off), prepared by
+    // launch_hot_prepare (hot_n[0] vertices in hot_ids and hot_bits, hot_n[1] the
+    // threshold); h0 holds the initial counts (n).
+    const uint32_t* h0;
+    int32_t hot_max;
+    int32_t pad1;
+    const uint32_t* hot_bits;
+    const uint32_t* hot_n;
+    const int32_t* hot_ids;
 };
+constexpr int kSelectHotBuckets = 4096;   // entries of SelInst::cnt_hist
+constexpr int kSelectHotPerBlock = 4096;  // hot vertices one block of the launch keeps at most
 constexpr int kMaxCoopGrid = 1024;   // blocks of a cooperative selection launch at most
 // Arrival counters of a hierarchical grid barrier (zeroed before each launch): block b
 // arrives on sub[b % 16]; the last arrival of a group bumps top; all wait for top.

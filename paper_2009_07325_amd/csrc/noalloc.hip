@@ -88,6 +88,12 @@ int64_t carve(unsigned char* base, const imm_pool* p, int64_t count, int32_t k_t
     w->seg[0].off = c.take<int64_t>(n + 1);
     w->seg[0].inv = c.take<uint32_t>(members);
     w->seg[0].cap = members;
+    const int32_t hot_max = select_hot_max(n);
+    w->hot_bits = c.take<uint32_t>((n + 31) / 32);
+    w->cnt_hist = c.take<uint32_t>(kSelectHotBuckets);
+    w->hot_n = c.take<uint32_t>(2);
+    w->hot_ids = c.take<int32_t>(hot_max);
+    w->hot_cap = hot_max;
     L->d_inst = c.take<SelInst>(1);
     L->bar = c.take<GridBarrier>(1);
     L->cap = 1;
@@ -149,7 +155,7 @@ extern "C" imm_status imm_select_seeds_noalloc(const imm_pool* pc, int64_t first
     {
         NoAllocGuard guard;
         SelInst si;
-        st = select_prepare(p, &w, first, count, k, s, &si, false);
+        st = select_prepare(p, &w, first, count, k, s, &si, false, true);
         if (st == IMM_OK) {
             SelectWs* wp = &w;
             st = select_run(&L, &wp, &si, 1, s);

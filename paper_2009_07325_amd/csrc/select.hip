@@ -383,137 +383,395 @@ __device__ __forceinline__ void block_key_store(unsigned long long best, unsigne
     __syncthreads();
 }
 
+// ---- hot set of a single-instance selection --------------------------------------------
+// Counters only decrease, so a vertex whose count is at most C can be the argmax only once
+// every other count is at most C.  With C the smallest threshold that leaves at most
+// hot_max vertices above it ("hot"), a round whose best hot count exceeds C has found the
+// exact argmax without reading any other counter, and the counters of cold vertices are
+// not needed at all until then: they are not decremented.  On the R-MAT workloads the
+// 16384 most frequent vertices leave every one of their greedy rounds in hot mode and
+// carry 40-60% of the decrements.  The first round whose best hot count is at most C
+// recounts every counter exactly (initial counts minus the covered sets, chosen vertices
+// -1 again) and the selection continues over all vertices.
+constexpr int kHotBuckets = kSelectHotBuckets;   // counts 0 .. 4094 exact, 4095: 4095 or more
+constexpr int kHotPerThread = kSelectHotPerBlock / kCoopBlock;   // hot vertices per thread
+static_assert(kHotBuckets == 4 * kCoopBlock, "the threshold search gives each thread 4 buckets");
+static_assert(kHotPerThread * kCoopBlock == kSelectHotPerBlock, "hot vertices per block");
+constexpr int32_t kHotOff = 0x7FFFFFFF;
+
+// h[v] = hist[v] for the selection's counters, and the histogram of those counts into
+// cnt_hist (zeroed): counts 0..3 by wave ballots, the rest by LDS atomics, each block's
+// non-zero buckets added to cnt_hist.
+__global__ __launch_bounds__(kCoopBlock) void k_hot_counts(const uint32_t* __restrict__ hist,
+                                                           int32_t* __restrict__ h, int64_t n,
+                                                           uint32_t* __restrict__ cnt_hist) {
+    __shared__ uint32_t chist[kHotBuckets];
+    const int tid = threadIdx.x, lane = lane_id();
+    for (int i = tid; i < kHotBuckets; i += kCoopBlock) chist[i] = 0;
+    __syncthreads();
+    uint32_t small[4] = {0u, 0u, 0u, 0u};
+    for (int64_t b0 = (int64_t)blockIdx.x * kCoopBlock; b0 < n; b0 += (int64_t)gridDim.x * kCoopBlock) {
+        const int64_t v = b0 + tid;
+        int32_t c = -1;
+        if (v < n) {
+            c = (int32_t)hist[v];
+            h[v] = c;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) small[q] += (uint32_t)__popcll(ballot(c == q));
+        if (c >= 4) atomicAdd(&chist[c < kHotBuckets - 1 ? c : kHotBuckets - 1], 1u);
+    }
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q)
+            if (small[q]) atomicAdd(&chist[q], small[q]);
+    __syncthreads();
+    for (int i = tid; i < kHotBuckets; i += kCoopBlock)
+        if (chist[i]) atomicAdd(cnt_hist + i, chist[i]);
+}
+
+// The hot threshold C (the smallest count below the last bucket with at most hot_max
+// counts above it) and the hot list {v : h[v] > C} (any order) with its bitmap (zeroed).
+// Every block finds C from cnt_hist; hot_n[0] = list length, hot_n[1] = C (kHotOff: no
+// hot set).
+__global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restrict__ h, int64_t n,
+                                                         const uint32_t* __restrict__ cnt_hist,
+                                                         int32_t hot_max, uint32_t* __restrict__ hot_bits,
+                                                         int32_t* __restrict__ hot_ids,
+                                                         uint32_t* __restrict__ hot_n) {
+    __shared__ int64_t pre[kCoopBlock + 1];
+    __shared__ int64_t wsum[kCoopWaves];
+    __shared__ int32_t s_thr;
+    const int tid = threadIdx.x, lane = lane_id();
+    // thread t holds buckets kHotBuckets - 1 - (4t + j), j = 0..3 (descending)
+    uint32_t cj[4];
+    int64_t local = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        cj[j] = cnt_hist[kHotBuckets - 1 - (4 * tid + j)];
+        local += cj[j];
+    }
+    block_excl_scan_i64(local, pre, wsum);
+    int64_t above = pre[tid];                    // counts in the buckets above this thread's
+    int32_t cand = kHotOff;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t b = kHotBuckets - 1 - (4 * tid + j);
+        if (b < kHotBuckets - 1 && above <= (int64_t)hot_max) cand = min(cand, b);
+        above += cj[j];
+    }
+    if (tid == 0) s_thr = kHotOff;
+    __syncthreads();
+    if (cand != kHotOff) atomicMin(&s_thr, cand);
+    __syncthreads();
+    const int32_t thr = s_thr;
+    if (blockIdx.x == 0 && tid == 0) hot_n[1] = (uint32_t)thr;
+    if (thr == kHotOff) return;
+    for (int64_t b0 = (int64_t)blockIdx.x * kCoopBlock; b0 < n; b0 += (int64_t)gridDim.x * kCoopBlock) {
+        const int64_t v = b0 + tid;
+        const bool hot = v < n && h[v] > thr;
+        const uint64_t m = ballot(hot);
+        if (m) {
+            uint32_t at = 0;
+            if (lane == 0) at = atomicAdd(hot_n, (uint32_t)__popcll(m));
+            at = __shfl(at, 0, kWave);
+            if (hot) {
+                hot_ids[at + lanes_below(m)] = (int32_t)v;
+                atomicOr(hot_bits + (v >> 5), 1u << (v & 31));
+            }
+        }
+    }
+}
+
+hipError_t launch_hot_prepare(const uint32_t* hist, int32_t* h, int64_t n, int32_t hot_max,
+                              uint32_t* cnt_hist, uint32_t* hot_bits, int32_t* hot_ids,
+                              uint32_t* hot_n, hipStream_t s) {
+    int64_t blocks = (n + kCoopBlock - 1) / kCoopBlock;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    k_hot_counts<<<(unsigned)blocks, kCoopBlock, 0, s>>>(hist, h, n, cnt_hist);
+    k_hot_list<<<(unsigned)blocks, kCoopBlock, 0, s>>>(h, n, cnt_hist, hot_max, hot_bits, hot_ids, hot_n);
+    return hipGetLastError();
+}
+
+struct CoopLds {
+    int64_t tile_pre[kMaxInst + 1];     // argmax tiles per instance, prefix
+    int64_t ent_pre[kMaxInst + 1];      // cover entries per instance, prefix
+    int64_t ent_beg[kMaxInst];
+    int32_t chosen[kMaxInst];           // each instance's vertex of this round
+    unsigned long long red[kCoopWaves];
+    int64_t wsum[kCoopWaves];
+    int64_t set_pre[kCoopBlock + 1];    // decrement batch: prefix of its sets' sizes
+    const int32_t* set_mem[kCoopBlock];
+    int32_t set_inst[kCoopBlock];
+    union {
+        DecCache dc;
+    } u;
+    unsigned char stopped[kMaxInst];    // estimation phase decided (failed)
+    int64_t seg_pre[kMaxSegs + 1];      // single instance: its entries per segment
+    int64_t seg_beg[kMaxSegs];
+    unsigned long long key;             // single instance: this round's argmax key
+    int32_t thr;
+    int32_t hot_cnt;                    // this block's share of the hot list ...
+    int32_t hot[kSelectHotPerBlock];    // ... kept for all rounds
+};
+
+// Decrements the counters of the members of every thread's set (len members at mem, of
+// instance li; len 0: none): the block scans the sizes and its waves share the flattened
+// members (consecutive lanes on consecutive members of a set, four per lane in flight),
+// each member found by a binary search over the prefix.  Skips each instance's chosen
+// vertex when skip_chosen, and vertices outside the hot set when hot_bits is set.  All
+// threads of the block.
+__device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t len, const int32_t* mem, int li,
+                          bool skip_chosen, const uint32_t* hot_bits) {
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    block_excl_scan_i64(len, S.set_pre, S.wsum);
+    S.set_mem[tid] = mem;
+    S.set_inst[tid] = li;
+    __syncthreads();
+    const int64_t total = S.set_pre[kCoopBlock];
+    for (int64_t q0 = (int64_t)wid * (4 * kWave); q0 < total; q0 += 4 * kCoopBlock) {
+        int32_t v[4], vi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = q0 + u * kWave + lane;
+            vi[u] = -1;
+            if (q < total) {
+                int lo = 0, hi = kCoopBlock;       // set_pre[lo] <= q < set_pre[lo + 1]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (S.set_pre[mid] <= q) lo = mid; else hi = mid;
+                }
+                v[u] = global(S.set_mem[lo])[q - S.set_pre[lo]];
+                vi[u] = S.set_inst[lo];
+            }
+        }
+        if (hot_bits) {
+            uint32_t w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] = vi[u] >= 0 ? global(hot_bits)[v[u] >> 5] : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (!((w[u] >> (v[u] & 31)) & 1u)) vi[u] = -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (vi[u] >= 0 && !(skip_chosen && v[u] == S.chosen[vi[u]]))
+                dec_counter(S.u.dc, inst, vi[u], v[u]);
+    }
+    __syncthreads();                           // the batch tables are rewritten next
+}
+
+// One round's argmax over tiles of kArgTile counters, any instance still selecting.  A
+// block's successive tiles of one instance share one block reduction (tiles are grouped by
+// instance, so an instance's tiles are consecutive).  A single-instance launch leaves each
+// block's maximum in bar->bkeys (reduced after the barrier); several instances merge theirs
+// into the instance's key with an atomic.
+__device__ void argmax_tiles(CoopLds& S, const SelInst* inst, int32_t ninst, int32_t round,
+                             int64_t ntiles, GridBarrier* bar) {
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    unsigned long long best = 0;
+    int cur = -1;                                    // instance of `best`, block-uniform
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int lo = 0, hi = ninst;                      // tile_pre[lo] <= t < tile_pre[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (S.tile_pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        const SelInst& I = inst[lo];
+        if (round >= I.k || S.stopped[lo]) continue;   // uniform across the block
+        if (lo != cur) {
+            if (cur >= 0) block_key_max(best, global(inst[cur].keys) + round, S.red, lane, wid, tid);
+            cur = lo;
+            best = 0;
+        }
+        // partition matroid: the parts that already hold part_k chosen elements
+        uint64_t full = 0;
+        if (I.part_n > 0) {
+            const int32_t parts = I.n / I.part_n;
+            const int32_t tk = lane < parts ? ld_co(global(I.taken) + lane) : 0;
+            full = ballot(lane < parts && tk >= I.part_k);
+        }
+        const IMM_GLOBAL int32_t* h = global(I.h);
+        // up to kArgGroup of the block's successive tiles of this instance are loaded
+        // together
+        const int64_t left = (S.tile_pre[lo + 1] - t + gridDim.x - 1) / gridDim.x;
+        const int m = left < kArgGroup ? (int)left : kArgGroup;
+        const int64_t base = (t - S.tile_pre[lo]) * kArgTile;
+        const int64_t step = (int64_t)gridDim.x * kArgTile;
+        int32_t c[4 * kArgGroup];
+#pragma unroll
+        for (int j = 0; j < 4 * kArgGroup; ++j) {
+            const int64_t v = base + (j >> 2) * step + (j & 3) * kCoopBlock + tid;
+            c[j] = (j >> 2) < m && v < I.n ? ld_co(h + v) : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4 * kArgGroup; ++j) {
+            const int64_t v = base + (j >> 2) * step + (j & 3) * kCoopBlock + tid;
+            if (full != 0 && c[j] >= 0 && ((full >> ((uint32_t)v / (uint32_t)I.part_n)) & 1ull))
+                c[j] = -1;
+            if (c[j] >= 0) {
+                const unsigned long long key = ((unsigned long long)(uint32_t)(c[j] + 1) << 32) |
+                                               (unsigned long long)(0xFFFFFFFFu - (uint32_t)v);
+                best = key > best ? key : best;
+            }
+        }
+        t += (int64_t)(m - 1) * gridDim.x;
+    }
+    if (ninst == 1) {
+        block_key_store(best, bar->bkeys + blockIdx.x, S.red, lane, wid, tid);
+    } else if (cur >= 0) {
+        block_key_max(best, global(inst[cur].keys) + round, S.red, lane, wid, tid);
+    }
+}
+
+// Single instance: the maximum of the blocks' keys, into S.key.  All threads of the block.
+__device__ __forceinline__ void reduce_block_keys(CoopLds& S, GridBarrier* bar) {
+    const int tid = threadIdx.x, lane = lane_id();
+    if (tid < kWave) {
+        unsigned long long k = 0;
+        for (int b = lane; b < (int)gridDim.x; b += kWave) {
+            const unsigned long long x = ld_co(bar->bkeys + b);
+            k = x > k ? x : k;
+        }
+        k = wave_max_u64(k);
+        if (lane == 0) S.key = k;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __restrict__ inst,
                                                             int32_t ninst, int32_t maxk,
                                                             GridBarrier* bar) {
-    __shared__ int64_t tile_pre[kMaxInst + 1];    // argmax tiles per instance, prefix
-    __shared__ int64_t ent_pre[kMaxInst + 1];     // cover entries per instance, prefix
-    __shared__ int64_t ent_beg[kMaxInst];
-    __shared__ int32_t chosen[kMaxInst];          // each instance's vertex of this round
-    __shared__ unsigned long long red[kCoopWaves];
-    __shared__ int64_t wsum[kCoopWaves];
-    __shared__ int64_t set_pre[kCoopBlock + 1];   // cover batch: prefix of new sets' sizes
-    __shared__ const int32_t* set_mem[kCoopBlock];
-    __shared__ int32_t set_inst[kCoopBlock];
-    __shared__ DecCache dc;
-    __shared__ unsigned char stopped[kMaxInst];   // estimation phase decided (failed)
-    __shared__ int64_t seg_pre[kMaxSegs + 1];     // single instance: its entries per segment
-    __shared__ int64_t seg_beg[kMaxSegs];
-    for (int i = threadIdx.x; i < kDecSlots; i += blockDim.x) {
-        dc.key[i] = kDecEmpty;
-        dc.cnt[i] = 0;
-    }
-    if (threadIdx.x < kMaxInst) stopped[threadIdx.x] = 0;
+    __shared__ CoopLds S;
+    if (threadIdx.x < kMaxInst) S.stopped[threadIdx.x] = 0;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const bool solo = ninst == 1;
     unsigned int epoch = 0;
     // instance prefixes are computed one instance per thread (kMaxInst == kCoopBlock); the
     // tables past ninst repeat the total
-    block_excl_scan_i64(tid < ninst ? (inst[tid].n + kArgTile - 1) / kArgTile : 0, tile_pre, wsum);
-    const int64_t ntiles = tile_pre[ninst];
+    block_excl_scan_i64(tid < ninst ? (inst[tid].n + kArgTile - 1) / kArgTile : 0, S.tile_pre, S.wsum);
+    const int64_t ntiles = S.tile_pre[ninst];
+
+    // ---- hot set (single instance with hot_max > 0), prepared by k_hot_counts and
+    // k_hot_list: this block's share of the list is kept in LDS for all rounds ----
+    int32_t thr = kHotOff;
+    if (solo && inst[0].hot_max > 0) {
+        const SelInst& I = inst[0];
+        thr = (int32_t)I.hot_n[1];
+        if (thr != kHotOff) {
+            const int64_t H = I.hot_n[0];
+            const int64_t per = (H + gridDim.x - 1) / gridDim.x;
+            const int64_t lo = min(per * blockIdx.x, H);
+            const int64_t cnt = min(per, H - lo);
+            for (int64_t i = tid; i < cnt; i += kCoopBlock) S.hot[i] = I.hot_ids[lo + i];
+            if (tid == 0) S.hot_cnt = (int32_t)cnt;
+        }
+    }
+    for (int i = threadIdx.x; i < kDecSlots; i += blockDim.x) {
+        S.u.dc.key[i] = kDecEmpty;
+        S.u.dc.cnt[i] = 0;
+    }
+    __syncthreads();
 
     for (int32_t round = 0; round < maxk; ++round) {
         // coverage after the previous rounds (nothing adds to it before the next barrier);
         // thread i keeps instance i's
         const int64_t cov_before = tid < ninst ? (int64_t)ld_co(global(inst[tid].n_covered)) : 0;
-        // ---- argmax: tiles of kArgTile counters, any instance still selecting ----
-        // A block's successive tiles of one instance share one block reduction (tiles are
-        // grouped by instance, so an instance's tiles are consecutive).  A single-instance
-        // launch leaves each block's maximum in bar->bkeys (reduced after the barrier);
-        // several instances merge theirs into the instance's key with an atomic.
-        unsigned long long best = 0;
-        int cur = -1;                                    // instance of `best`, block-uniform
-        for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-            int lo = 0, hi = ninst;                      // tile_pre[lo] <= t < tile_pre[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (tile_pre[mid] <= t) lo = mid; else hi = mid;
-            }
-            const SelInst& I = inst[lo];
-            if (round >= I.k || stopped[lo]) continue;   // uniform across the block
-            if (lo != cur) {
-                if (cur >= 0) block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
-                cur = lo;
-                best = 0;
-            }
-            // partition matroid: the parts that already hold part_k chosen elements
-            uint64_t full = 0;
-            if (I.part_n > 0) {
-                const int32_t parts = I.n / I.part_n;
-                const int32_t tk = lane < parts ? ld_co(global(I.taken) + lane) : 0;
-                full = ballot(lane < parts && tk >= I.part_k);
-            }
-            const IMM_GLOBAL int32_t* h = global(I.h);
-            // up to kArgGroup of the block's successive tiles of this instance are loaded
-            // together
-            const int64_t left = (tile_pre[lo + 1] - t + gridDim.x - 1) / gridDim.x;
-            const int m = left < kArgGroup ? (int)left : kArgGroup;
-            const int64_t base = (t - tile_pre[lo]) * kArgTile;
-            const int64_t step = (int64_t)gridDim.x * kArgTile;
-            int32_t c[4 * kArgGroup];
+        // ---- argmax (a second time, over every vertex, after leaving hot mode) ----
+        for (;;) {
+            if (thr != kHotOff) {
+                const SelInst& I = inst[0];
+                unsigned long long best = 0;
+                if (round < I.k && !S.stopped[0]) {
+                    uint64_t full = 0;
+                    if (I.part_n > 0) {
+                        const int32_t parts = I.n / I.part_n;
+                        const int32_t tk = lane < parts ? ld_co(global(I.taken) + lane) : 0;
+                        full = ballot(lane < parts && tk >= I.part_k);
+                    }
+                    int32_t c[kHotPerThread], hv[kHotPerThread];
 #pragma unroll
-            for (int j = 0; j < 4 * kArgGroup; ++j) {
-                const int64_t v = base + (j >> 2) * step + (j & 3) * kCoopBlock + tid;
-                c[j] = (j >> 2) < m && v < I.n ? ld_co(h + v) : -1;
-            }
+                    for (int j = 0; j < kHotPerThread; ++j) {
+                        const int i = tid + j * kCoopBlock;
+                        hv[j] = i < S.hot_cnt ? S.hot[i] : -1;
+                        c[j] = hv[j] >= 0 ? ld_co(global(I.h) + hv[j]) : -1;
+                    }
 #pragma unroll
-            for (int j = 0; j < 4 * kArgGroup; ++j) {
-                const int64_t v = base + (j >> 2) * step + (j & 3) * kCoopBlock + tid;
-                if (full != 0 && c[j] >= 0 && ((full >> ((uint32_t)v / (uint32_t)I.part_n)) & 1ull))
-                    c[j] = -1;
-                if (c[j] >= 0) {
-                    const unsigned long long key = ((unsigned long long)(uint32_t)(c[j] + 1) << 32) |
-                                                   (unsigned long long)(0xFFFFFFFFu - (uint32_t)v);
-                    best = key > best ? key : best;
+                    for (int j = 0; j < kHotPerThread; ++j) {
+                        const uint32_t v = (uint32_t)hv[j];
+                        if (full != 0 && c[j] >= 0 && ((full >> (v / (uint32_t)I.part_n)) & 1ull)) c[j] = -1;
+                        if (c[j] >= 0) {
+                            const unsigned long long key = ((unsigned long long)(uint32_t)(c[j] + 1) << 32) |
+                                                           (unsigned long long)(0xFFFFFFFFu - v);
+                            best = key > best ? key : best;
+                        }
+                    }
                 }
+                block_key_store(best, bar->bkeys + blockIdx.x, S.red, lane, wid, tid);
+            } else {
+                argmax_tiles(S, inst, ninst, round, ntiles, bar);
             }
-            t += (int64_t)(m - 1) * gridDim.x;
+            if (!grid_sync(bar, epoch)) return;
+            if (solo) reduce_block_keys(S, bar);
+            if (thr == kHotOff || round >= inst[0].k || S.stopped[0] ||
+                (S.key != 0 && (int64_t)(S.key >> 32) - 1 > (int64_t)thr))
+                break;
+            // the best hot count is no longer above every cold count: recount all counters
+            // exactly and leave hot mode
+            const SelInst& I = inst[0];
+            IMM_GLOBAL int32_t* h = global(I.h);
+            for (int64_t v = (int64_t)blockIdx.x * kCoopBlock + tid; v < I.n; v += (int64_t)gridDim.x * kCoopBlock)
+                st_co(h + v, (int32_t)global(I.h0)[v]);
+            if (!grid_sync(bar, epoch)) return;
+            const int64_t s_lo = I.count * (int64_t)blockIdx.x / gridDim.x;
+            const int64_t s_hi = I.count * ((int64_t)blockIdx.x + 1) / gridDim.x;
+            for (int64_t sb = s_lo; sb < s_hi; sb += kCoopBlock) {
+                const int64_t rel = sb + tid;
+                int64_t len = 0;
+                const int32_t* mem = nullptr;
+                if (rel < s_hi && ld_co(global(I.covered) + rel) != 0u) {
+                    mem = I.ids + global(I.rr_start)[I.first + rel];
+                    len = global(I.rr_len)[I.first + rel];
+                }
+                dec_batch(S, inst, len, mem, 0, false, nullptr);
+            }
+            dec_flush(S.u.dc, inst);
+            if (!grid_sync(bar, epoch)) return;
+            if (blockIdx.x == 0)
+                for (int j = tid; j < round; j += kCoopBlock) st_co(h + ld_co(global(I.seeds) + j), -1);
+            thr = kHotOff;
+            if (!grid_sync(bar, epoch)) return;
         }
-        if (solo) {
-            block_key_store(best, bar->bkeys + blockIdx.x, red, lane, wid, tid);
-        } else if (cur >= 0) {
-            block_key_max(best, global(inst[cur].keys) + round, red, lane, wid, tid);
-        }
-        if (!grid_sync(bar, epoch)) return;
         // ---- cover: sets containing each instance's new seed ----
         // Every block reads the same final keys and coverage, so every block takes the same
         // stop decisions.
-        unsigned long long solo_key = 0;
-        if (solo && wid == 0) {
-            unsigned long long k = 0;
-            for (int b = lane; b < (int)gridDim.x; b += kWave) {
-                const unsigned long long x = ld_co(bar->bkeys + b);
-                k = x > k ? x : k;
-            }
-            solo_key = wave_max_u64(k);
-        }
         int64_t cnt = 0;
         bool live = false;
-        if (tid < ninst && round < inst[tid].k && !stopped[tid]) {
+        if (tid < ninst && round < inst[tid].k && !S.stopped[tid]) {
             const SelInst& I = inst[tid];
-            const unsigned long long key = solo ? solo_key : ld_co(global(I.keys) + round);
+            const unsigned long long key = solo ? S.key : ld_co(global(I.keys) + round);
             const int64_t gain = key ? (int64_t)(key >> 32) - 1 : 0;
             const int64_t bound = cov_before + (int64_t)(I.k - round) * gain;
             if (I.need > 0 && bound < I.need) {
-                stopped[tid] = 1;
+                S.stopped[tid] = 1;
             } else {
                 live = true;
                 const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
-                chosen[tid] = u;
+                S.chosen[tid] = u;
                 if (I.nseg > 1) {              // only in single-instance launches
                     int64_t acc = 0;
                     for (int j = 0; j < I.nseg; ++j) {
                         const int64_t b = global(I.seg_off[j])[u];
-                        seg_beg[j] = b;
-                        seg_pre[j] = acc;
+                        S.seg_beg[j] = b;
+                        S.seg_pre[j] = acc;
                         acc += global(I.seg_off[j])[u + 1] - b;
                     }
-                    seg_pre[I.nseg] = acc;
-                    ent_beg[tid] = 0;
+                    S.seg_pre[I.nseg] = acc;
+                    S.ent_beg[tid] = 0;
                     cnt = acc;
                 } else {
                     const int64_t beg = global(I.inv_off)[u];
-                    ent_beg[tid] = beg;
+                    S.ent_beg[tid] = beg;
                     cnt = global(I.inv_off)[u + 1] - beg;
                 }
                 if (blockIdx.x == 0) {
@@ -527,15 +785,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             }
         }
         if (!__syncthreads_or(live)) return;            // every instance finished or stopped
-        block_excl_scan_i64(cnt, ent_pre, wsum);
-        const int64_t nent = ent_pre[ninst];
+        block_excl_scan_i64(cnt, S.ent_pre, S.wsum);
+        const int64_t nent = S.ent_pre[ninst];
         // Block b takes entries [nent b / G, nent (b+1) / G) in batches of one per thread:
-        // each thread tests and marks its entry's set; the sizes of the batch's newly covered
-        // sets are scanned over the block, and the block's waves then share the flattened
-        // members (consecutive lanes on consecutive members of a set, four per lane in
-        // flight), each member found by a binary search over the batch's prefix.
+        // each thread tests and marks its entry's set, and the batch's newly covered sets
+        // are decremented together.
         const int64_t e_lo = nent * (int64_t)blockIdx.x / gridDim.x;
         const int64_t e_hi = nent * ((int64_t)blockIdx.x + 1) / gridDim.x;
+        const uint32_t* hot_bits = thr != kHotOff ? inst[0].hot_bits : nullptr;
         unsigned long long mine = 0;
         int mine_inst = -1;
         for (int64_t eb = e_lo; eb < e_hi; eb += kCoopBlock) {
@@ -548,18 +805,18 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 int lo = 0, hi = ninst;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (ent_pre[mid] <= e) lo = mid; else hi = mid;
+                    if (S.ent_pre[mid] <= e) lo = mid; else hi = mid;
                 }
                 li = lo;
                 const SelInst& I = inst[lo];
                 uint32_t rel;
                 if (I.nseg > 1) {
-                    const int64_t q = e - ent_pre[lo];
+                    const int64_t q = e - S.ent_pre[lo];
                     int j = 0;
-                    while (j + 1 < I.nseg && seg_pre[j + 1] <= q) ++j;
-                    rel = global(I.seg_inv[j])[seg_beg[j] + (q - seg_pre[j])];
+                    while (j + 1 < I.nseg && S.seg_pre[j + 1] <= q) ++j;
+                    rel = global(I.seg_inv[j])[S.seg_beg[j] + (q - S.seg_pre[j])];
                 } else {
-                    rel = global(I.inv)[ent_beg[lo] + (e - ent_pre[lo])];
+                    rel = global(I.inv)[S.ent_beg[lo] + (e - S.ent_pre[lo])];
                 }
                 fresh = ld_co(global(I.covered) + rel) == 0u;
                 if (fresh) {
@@ -581,35 +838,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 mine += (unsigned long long)__popcll(mx);
                 pending &= ~mx;
             }
-            block_excl_scan_i64(len, set_pre, wsum);
-            set_mem[tid] = mem;
-            set_inst[tid] = li;
-            __syncthreads();
-            const int64_t total = set_pre[kCoopBlock];
-            for (int64_t q0 = (int64_t)wid * (4 * kWave); q0 < total; q0 += 4 * kCoopBlock) {
-                int32_t v[4], vi[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t q = q0 + u * kWave + lane;
-                    vi[u] = -1;
-                    if (q < total) {
-                        int lo = 0, hi = kCoopBlock;   // set_pre[lo] <= q < set_pre[lo + 1]
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (set_pre[mid] <= q) lo = mid; else hi = mid;
-                        }
-                        v[u] = global(set_mem[lo])[q - set_pre[lo]];
-                        vi[u] = set_inst[lo];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (vi[u] >= 0 && v[u] != chosen[vi[u]]) dec_counter(dc, inst, vi[u], v[u]);
-            }
-            __syncthreads();                    // the batch tables are rewritten next
+            dec_batch(S, inst, len, mem, li, true, hot_bits);
         }
         if (mine && lane == 0) atomic_add_agent(global(inst[mine_inst].n_covered), mine);
-        dec_flush(dc, inst);
+        dec_flush(S.u.dc, inst);
         if (!grid_sync(bar, epoch)) return;
     }
 }
