@@ -398,6 +398,7 @@ constexpr int kHotPerThread = kSelectHotPerBlock / kCoopBlock;   // hot vertices
 static_assert(kHotBuckets == 4 * kCoopBlock, "the threshold search gives each thread 4 buckets");
 static_assert(kHotPerThread * kCoopBlock == kSelectHotPerBlock, "hot vertices per block");
 constexpr int32_t kHotOff = 0x7FFFFFFF;
+constexpr int kHotListPer = 16;          // vertices per thread when the hot list is built
 
 // h[v] = hist[v] for the selection's counters, and the histogram of those counts into
 // cnt_hist (zeroed): counts 0..3 by wave ballots, the rest by LDS atomics, each block's
@@ -466,18 +467,30 @@ __global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restri
     const int32_t thr = s_thr;
     if (blockIdx.x == 0 && tid == 0) hot_n[1] = (uint32_t)thr;
     if (thr == kHotOff) return;
-    for (int64_t b0 = (int64_t)blockIdx.x * kCoopBlock; b0 < n; b0 += (int64_t)gridDim.x * kCoopBlock) {
-        const int64_t v = b0 + tid;
-        const bool hot = v < n && h[v] > thr;
-        const uint64_t m = ballot(hot);
-        if (m) {
-            uint32_t at = 0;
-            if (lane == 0) at = atomicAdd(hot_n, (uint32_t)__popcll(m));
-            at = __shfl(at, 0, kWave);
-            if (hot) {
-                hot_ids[at + lanes_below(m)] = (int32_t)v;
-                atomicOr(hot_bits + (v >> 5), 1u << (v & 31));
-            }
+    // the block's contiguous range of vertices, kHotListPer per thread: count its hot
+    // vertices, reserve their places with one atomic, then write them
+    const int64_t lo = (int64_t)blockIdx.x * kCoopBlock * kHotListPer;
+    int32_t c[kHotListPer];
+    int32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < kHotListPer; ++j) {
+        const int64_t v = lo + (int64_t)j * kCoopBlock + tid;
+        c[j] = v < n ? h[v] : -1;
+        mine += c[j] > thr;
+    }
+    block_excl_scan_i64(mine, pre, wsum);
+    const int64_t total = pre[kCoopBlock];
+    if (total == 0) return;
+    __shared__ uint32_t s_base;
+    if (tid == 0) s_base = atomicAdd(hot_n, (uint32_t)total);
+    __syncthreads();
+    uint32_t at = s_base + (uint32_t)pre[tid];
+#pragma unroll
+    for (int j = 0; j < kHotListPer; ++j) {
+        const int64_t v = lo + (int64_t)j * kCoopBlock + tid;
+        if (c[j] > thr) {
+            hot_ids[at++] = (int32_t)v;
+            atomicOr(hot_bits + (v >> 5), 1u << (v & 31));
         }
     }
 }
@@ -489,7 +502,9 @@ hipError_t launch_hot_prepare(const uint32_t* hist, int32_t* h, int64_t n, int32
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     k_hot_counts<<<(unsigned)blocks, kCoopBlock, 0, s>>>(hist, h, n, cnt_hist);
-    k_hot_list<<<(unsigned)blocks, kCoopBlock, 0, s>>>(h, n, cnt_hist, hot_max, hot_bits, hot_ids, hot_n);
+    const int64_t lblocks = (n + (int64_t)kCoopBlock * kHotListPer - 1) / ((int64_t)kCoopBlock * kHotListPer);
+    k_hot_list<<<(unsigned)(lblocks > 0 ? lblocks : 1), kCoopBlock, 0, s>>>(h, n, cnt_hist, hot_max, hot_bits,
+                                                                          hot_ids, hot_n);
     return hipGetLastError();
 }
 
@@ -519,8 +534,8 @@ struct CoopLds {
 // instance li; len 0: none): the block scans the sizes and its waves share the flattened
 // members (consecutive lanes on consecutive members of a set, four per lane in flight),
 // each member found by a binary search over the prefix.  Skips each instance's chosen
-// vertex when skip_chosen, and vertices outside the hot set when hot_bits is set.  All
-// threads of the block.
+// vertex when skip_chosen, and, in batches of more than 4 x kCoopBlock members, vertices
+// outside the hot set when hot_bits is set.  All threads of the block.
 __device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t len, const int32_t* mem, int li,
                           bool skip_chosen, const uint32_t* hot_bits) {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
@@ -545,7 +560,9 @@ __device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t 
                 vi[u] = S.set_inst[lo];
             }
         }
-        if (hot_bits) {
+        if (hot_bits && total > 4 * kCoopBlock) {
+            // cold counters are never read in hot mode (and the recount resets them), so a
+            // small batch skips the bitmap test and its dependent load
             uint32_t w[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) w[u] = vi[u] >= 0 ? global(hot_bits)[v[u] >> 5] : 0u;
@@ -818,11 +835,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 } else {
                     rel = global(I.inv)[S.ent_beg[lo] + (e - S.ent_pre[lo])];
                 }
+                // the set's place is loaded together with its flag (most entries of late
+                // rounds are covered already; the extra loads save a dependent latency)
+                const int64_t st = global(I.rr_start)[I.first + rel];
+                const int32_t ln = global(I.rr_len)[I.first + rel];
                 fresh = ld_co(global(I.covered) + rel) == 0u;
                 if (fresh) {
                     st_co(global(I.covered) + rel, 1u);
-                    mem = I.ids + global(I.rr_start)[I.first + rel];
-                    len = global(I.rr_len)[I.first + rel];
+                    mem = I.ids + st;
+                    len = ln;
                 }
             }
             // covered counts per instance (an instance's entries are contiguous)
