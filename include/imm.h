@@ -175,8 +175,8 @@ imm_status imm_select_seeds(imm_pool* p, int64_t first, int64_t count, int32_t k
  *   p, first, count, k   as imm_select_seeds (multi-round pools: k per round)
  *   seeds_out            int32[k x rounds], host, required
  *   covered_out          int64, host, or NULL
- * The workspace needs 20 n + 4 count + 4 (ids held by the pool) + 12 k bytes, plus 4 n
- * when the range is not the pool's whole prefix, plus a few KiB
+ * The workspace needs about 20.2 n + 4 count + 4 (ids held by the pool) + 12 k bytes,
+ * plus 4 n when the range is not the pool's whole prefix, plus about 100 KiB
  * (imm_select_noalloc_bytes reports the exact figure); larger requests return
  * IMM_ECAPACITY before anything runs.  All calls on one device share its array: calls
  * that overlap on one device (other host threads, other streams) race and must not be
