@@ -271,96 +271,197 @@ def bench_batch(args) -> int:
 # ---------------------------------------------------------------------------------------
 # Served workload: one resident graph, a Poisson stream of IMM queries
 # ---------------------------------------------------------------------------------------
+def _serve_stream(imm, srv, qs, qps, seed, tag):
+    """Submits queries qs to server srv as a Poisson stream at `qps` offered queries/s and
+    waits for all; returns (elapsed, results, rejected, oom) with results[i] = (seeds, info)
+    or None for a query the server rejected (IMM_ECAPACITY: its RR sets cannot fit) or
+    that failed to get device memory while running (IMM_ENOMEM)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / qps, len(qs))
+    t0 = time.perf_counter()
+    tickets, at = [], 0.0
+    for q, gap in zip(qs, gaps):
+        at += gap
+        delay = t0 + at - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(imm.imm_server_submit(srv, q["k"], q["eps"], 1.0, q["model"]))
+        if len(tickets) % 25 == 0:
+            log(f"  [{tag}] submitted {len(tickets)}/{len(qs)}")
+    results, rejected, oom = [], 0, 0
+    for tk, q in zip(tickets, qs):
+        try:
+            results.append(imm.imm_server_wait(srv, tk, q["k"]))
+        except imm.ImmError as e:
+            if e.status not in (2, 3):          # IMM_ENOMEM, IMM_ECAPACITY
+                raise
+            results.append(None)
+            rejected += e.status == 3
+            oom += e.status == 2
+        log(f"  [{tag}] finished {len(results)}/{len(qs)} ({'IC' if q['model'] == 0 else 'LT'} "
+            f"k={q['k']} eps={q['eps']}{', rejected' if results[-1] is None else ''}) at "
+            f"{time.perf_counter() - t0:.1f}s")
+    return time.perf_counter() - t0, results, rejected, oom
+
+
 def bench_serve(args) -> int:
+    """Served line: one resident R-MAT graph (scale 24), IC queries on its trivalency
+    probabilities and LT queries on weighted-cascade LT, a seeded Poisson stream of queries
+    (k ~ U{10..200}, eps in {0.2, 0.1, 0.05}, model IC or LT) admitted by device memory.
+    One-at-a-time throughput X (queries answered per second, completed or rejected, through
+    the same server with one query in flight) is measured first, and the same queries are
+    then submitted at once to a server with up to max_active in flight (its capacity on the
+    same work); the stream then runs at 0.5X, X and 2X.  Every server first answers the same
+    two warm-up queries (IC and LT, k = 10, eps = 0.2), so that each starts with its pools'
+    pilot sets drawn and the IC pool's first coverage seen."""
     import numpy as np
     import paper_2009_07325_amd as imm
-    from synth import configs
+    from synth import configs, graphs
     t = time.perf_counter()
-    from synth import graphs
-    g, _ = configs.c5_graph(scale=args.c5_scale,
-                            progress=lambda msg: log(f"  graph: {msg} ({time.perf_counter() - t:.0f}s)"))
+    g, triv = configs.c5_graph(scale=args.c5_scale,
+                               progress=lambda msg: log(f"  graph: {msg} ({time.perf_counter() - t:.0f}s)"))
     log(f"C5 graph n={g.n} m={g.m} built in {time.perf_counter() - t:.1f}s")
-    # Weighted-cascade IC: with trivalency probabilities every RR set of this graph holds a
-    # giant live component (~2e5 members), so theta * |RR| for eps <= 0.2 exceeds the
-    # device memory by one to three orders of magnitude.
-    p = graphs.weighted_cascade(g)
+    p = triv if args.c5_ic == "trivalency" else graphs.weighted_cascade(g)
     imm.imm_init(0)
     gg = imm.Graph.from_arrays(g.n, g.in_off, g.in_src, ic_p=p, lt_w=None, lt=True)
-    del p
-    rng = np.random.Generator(np.random.PCG64(5))
-    nq = args.queries
-    qs = [dict(k=int(rng.integers(10, 201)), eps=float(rng.choice([0.2, 0.1, 0.05])),
-               model=int(rng.integers(0, 2))) for _ in range(nq)]
-    gaps = rng.exponential(1.0 / args.qps, nq)
+    del p, triv
     seeds = (configs.C5_POOL_SEED_IC, configs.C5_POOL_SEED_LT)
-    srv = imm.imm_server_create(gg.handle, seeds[0], seeds[1], args.hbm_budget_gib << 30,
-                                args.max_active)
+    rng = np.random.Generator(np.random.PCG64(5))
+    total = args.queries + 2 * args.queries_side + args.calib
+    qs = [dict(k=int(rng.integers(10, 201)), eps=float(rng.choice([0.2, 0.1, 0.05])),
+               model=int(rng.integers(0, 2))) for _ in range(total)]
+    budget = args.hbm_budget_gib << 30
+    warm = [dict(k=10, eps=0.2, model=0), dict(k=10, eps=0.2, model=1)]
+
+    # 1. X: the calibration queries one at a time through the same server (max_active 1:
+    #    the same admission, resident pools reused), then the admitted ones cold (fresh
+    #    pools, as imm_solve) and warm (imm_solve_pool on resident pools) for comparison
+    calib = qs[:args.calib]
+    srv = imm.imm_server_create(gg.handle, seeds[0], seeds[1], budget, 1)
     try:
-        # warm-up: the first queries of each model grow the shared pools
-        for m in (imm.IMM_IC, imm.IMM_LT):
-            tk = imm.imm_server_submit(srv, 50, 0.1, 1.0, m)
-            imm.imm_server_wait(srv, tk, 50)
-        base = imm.imm_server_stats_get(srv)
-        log(f"warm-up done: pools IC {base['pool_sets_ic']} LT {base['pool_sets_lt']} sets")
-        t0 = time.perf_counter()
-        tickets, at = [], 0.0
-        for q, gap in zip(qs, gaps):
-            at += gap
-            delay = t0 + at - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets.append(imm.imm_server_submit(srv, q["k"], q["eps"], 1.0, q["model"]))
-            if len(tickets) % 50 == 0:
-                log(f"  submitted {len(tickets)}/{nq}")
-        results = []
-        for tk, q in zip(tickets, qs):
-            results.append(imm.imm_server_wait(srv, tk, q["k"]))
-            if len(results) % 25 == 0:
-                log(f"  completed {len(results)}/{nq} at {time.perf_counter() - t0:.1f}s")
-        elapsed = time.perf_counter() - t0
-        st = imm.imm_server_stats_get(srv)
+        for q in warm:
+            _serve_stream(imm, srv, [q], 1e6, 10, "warm-up")
+        t_one, res_one, rej_one, oom_one = _serve_stream(imm, srv, calib, 1e6, 11, "one at a time")
     finally:
         imm.imm_server_destroy(srv)
-    lat = np.array([i["t_total_s"] for _, i in results])
-    log(f"served {nq} queries in {elapsed:.2f}s; p50 {np.percentile(lat, 50):.3f}s "
-        f"p99 {np.percentile(lat, 99):.3f}s")
-    # one at a time: the first queries of the stream as plain solves
-    nseq = min(args.sequential, nq)
-    t1 = time.perf_counter()
+    ok = [i for i, r in enumerate(res_one) if r is not None]
+    x_rate = len(calib) / t_one if t_one > 0 else 1.0
+    log(f"one at a time: {len(calib)} queries in {t_one:.2f}s ({rej_one} rejected, {oom_one} out of "
+        f"memory) -> X = {x_rate:.2f} q/s")
+    imm.imm_release_cached_memory()
+    #    the same queries all at once, up to max_active in flight
+    srv = imm.imm_server_create(gg.handle, seeds[0], seeds[1], budget, args.max_active)
+    try:
+        for q in warm:
+            _serve_stream(imm, srv, [q], 1e6, 10, "warm-up")
+        t_sat, res_sat, rej_sat, oom_sat = _serve_stream(imm, srv, calib, 1e6, 11, "all at once")
+    finally:
+        imm.imm_server_destroy(srv)
+    imm.imm_release_cached_memory()
     mismatched = 0
-    for j in range(nseq):
-        q = qs[j]
-        s_alone, i_alone = imm.imm_solve(gg.handle, q["k"], q["eps"], 1.0, q["model"],
-                                         seeds[q["model"]])
-        mismatched += int(not np.array_equal(s_alone, results[j][0]) or
-                          i_alone["theta"] != results[j][1]["theta"])
-        log(f"  sequential {j + 1}/{nseq}: {time.perf_counter() - t1:.1f}s")
-    t_seq = time.perf_counter() - t1
+    for a, b in zip(res_one, res_sat):
+        if (a is None) != (b is None):
+            mismatched += 1
+        elif a is not None:
+            mismatched += int(not np.array_equal(a[0], b[0]) or a[1]["theta"] != b[1]["theta"])
+    lat_sat = [r[1]["t_total_s"] for r in res_sat if r is not None]
+    log(f"all at once: {len(calib)} queries in {t_sat:.2f}s ({rej_sat} rejected, {oom_sat} out of "
+        f"memory): {len(calib) / t_sat:.2f} q/s, {t_one / t_sat:.2f}x one at a time")
+    pools = [imm.Pool.create(gg, imm.IMM_IC, seeds[0]), imm.Pool.create(gg, imm.IMM_LT, seeds[1])]
+    for i in ok[:2]:
+        q = calib[i]
+        imm.imm_solve_pool(pools[q["model"]].handle, q["k"], q["eps"], 1.0, False)
+    t1 = time.perf_counter()
+    seq_lat = []
+    for i in ok:
+        q = calib[i]
+        t = time.perf_counter()
+        s_alone, i_alone = imm.imm_solve_pool(pools[q["model"]].handle, q["k"], q["eps"], 1.0, False)
+        seq_lat.append(time.perf_counter() - t)
+        mismatched += int(not np.array_equal(s_alone, res_one[i][0]) or
+                          i_alone["theta"] != res_one[i][1]["theta"])
+        log(f"  [warm] query {i} ({'IC' if q['model'] == 0 else 'LT'} k={q['k']} eps={q['eps']}): "
+            f"{seq_lat[-1]:.3f}s")
+    t_warm = time.perf_counter() - t1
+    del pools
+    imm.imm_release_cached_memory()
+    ncold = min(args.cold, len(ok))
+    t1 = time.perf_counter()
+    for i in ok[:ncold]:
+        q = calib[i]
+        s_alone, i_alone = imm.imm_solve(gg.handle, q["k"], q["eps"], 1.0, q["model"], seeds[q["model"]])
+        mismatched += int(not np.array_equal(s_alone, res_one[i][0]))
+    t_cold = time.perf_counter() - t1
+    imm.imm_release_cached_memory()
+
+    # 2. the stream at 0.5X, X and 2X (X: the headline)
+    runs = {}
+    rest = qs[args.calib:]
+    plan = [("0.5X", 0.5, rest[:args.queries_side]), ("X", 1.0, rest[args.queries_side:args.queries_side + args.queries]),
+            ("2X", 2.0, rest[args.queries_side + args.queries:])]
+    for tag, mult, part in plan:
+        if not part:
+            continue
+        srv = imm.imm_server_create(gg.handle, seeds[0], seeds[1], budget, args.max_active)
+        try:
+            for q in warm:                        # as in the calibration
+                _serve_stream(imm, srv, [q], 1e6, 10, "warm-up")
+            base = imm.imm_server_stats_get(srv)
+            elapsed, res, rej, oom = _serve_stream(imm, srv, part, mult * x_rate, 20 + int(mult * 10), tag)
+            st = imm.imm_server_stats_get(srv)
+        finally:
+            imm.imm_server_destroy(srv)
+        lat = np.array([r[1]["t_total_s"] for r in res if r is not None])
+        done = len(lat)
+        runs[tag] = {"offered_qps": mult * x_rate, "queries": len(part), "completed": done,
+                     "rejected": rej, "out_of_memory": oom, "completed_qps": done / elapsed,
+                     "answered_qps": len(part) / elapsed, "elapsed_s": elapsed,
+                     "p50_latency_s": float(np.percentile(lat, 50)) if done else None,
+                     "p99_latency_s": float(np.percentile(lat, 99)) if done else None,
+                     "mean_latency_s": float(lat.mean()) if done else None,
+                     "ticks": st["ticks"] - base["ticks"], "pool_sets_ic": st["pool_sets_ic"],
+                     "pool_sets_lt": st["pool_sets_lt"], "device_bytes": st["device_bytes"]}
+        log(f"[{tag}] {done}/{len(part)} completed ({rej} rejected) in {elapsed:.1f}s: "
+            f"{done / elapsed:.2f} q/s, p50 {runs[tag]['p50_latency_s']} p99 {runs[tag]['p99_latency_s']}")
+        imm.imm_release_cached_memory()
+    head = runs.get("X") or next(iter(runs.values()))
     out = {
         "metric": METRIC,
-        "value": nq / elapsed,
+        "value": head["completed_qps"],
         "unit": "IMM queries/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 2,
-        "ms_per_step": elapsed * 1e3,
+        "ms_per_step": head["elapsed_s"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic (seeded R-MAT graph, seeded query stream; no dataset)",
-        "config": {"workload": f"C5: R-MAT scale {args.c5_scale} (n={g.n}, m={g.m}), WC IC "
-                               f"and WC-LT; Poisson stream of {nq} queries at {args.qps} QPS, "
-                               "k ~ U{10..200}, eps in {0.2, 0.1, 0.05}, model IC or LT; "
-                               f"{args.max_active} active at most",
-                   "queries": nq, "qps_offered": args.qps},
-        "served": {"queries_s": nq / elapsed, "p50_latency_s": float(np.percentile(lat, 50)),
-                   "p99_latency_s": float(np.percentile(lat, 99)),
-                   "mean_latency_s": float(lat.mean()), "ticks": st["ticks"] - base["ticks"],
-                   "pool_sets_ic": st["pool_sets_ic"], "pool_sets_lt": st["pool_sets_lt"],
-                   "device_bytes": st["device_bytes"]},
-        "sequential": {"queries": nseq, "s_total": t_seq,
-                       "queries_s": nseq / t_seq if t_seq > 0 else None},
+        "config": {"workload": f"C5: R-MAT scale {args.c5_scale} (n={g.n}, m={g.m}), IC on "
+                               f"{args.c5_ic} probabilities, LT on weighted-cascade weights; "
+                               "Poisson stream, k ~ U{10..200}, eps in {0.2, 0.1, 0.05}, "
+                               f"model IC or LT; {args.max_active} active at most, "
+                               f"{args.hbm_budget_gib} GiB budget; offered rate X = one-at-a-time "
+                               "throughput of the same server",
+                   "queries_at_x": args.queries, "queries_side": args.queries_side,
+                   "ic_probabilities": args.c5_ic},
+        "served": runs,
+        "one_at_a_time": {"queries": len(calib), "completed": len(ok), "rejected": rej_one,
+                          "out_of_memory": oom_one, "s_total": t_one, "answered_qps": x_rate,
+                          "completed_qps": len(ok) / t_one if t_one > 0 else None},
+        "all_at_once": {"queries": len(calib), "completed": len(lat_sat), "rejected": rej_sat,
+                        "out_of_memory": oom_sat, "s_total": t_sat,
+                        "answered_qps": len(calib) / t_sat if t_sat > 0 else None,
+                        "completed_qps": len(lat_sat) / t_sat if t_sat > 0 else None,
+                        "p50_latency_s": _pct(lat_sat, 50), "p99_latency_s": _pct(lat_sat, 99),
+                        "speedup_vs_one_at_a_time": t_one / t_sat if t_sat > 0 else None},
+        "sequential_warm": {"queries": len(ok), "s_total": t_warm,
+                            "queries_s": len(ok) / t_warm if t_warm > 0 else None,
+                            "p50_s": _pct(seq_lat, 50), "p99_s": _pct(seq_lat, 99)},
+        "sequential_cold": {"queries": ncold, "s_total": t_cold,
+                            "queries_s": ncold / t_cold if t_cold > 0 else None},
         "results_equal_sequential": mismatched == 0,
     }
     print(json.dumps(out), flush=True)
@@ -463,11 +564,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
-    ap.add_argument("--queries", type=int, default=200, help="c5: queries in the stream")
-    ap.add_argument("--qps", type=float, default=20.0, help="c5: offered queries per second")
+    ap.add_argument("--queries", type=int, default=1000, help="c5: queries streamed at X")
+    ap.add_argument("--queries-side", type=int, default=300, help="c5: queries at 0.5X and at 2X each")
+    ap.add_argument("--calib", type=int, default=60, help="c5: queries that calibrate X")
+    ap.add_argument("--cold", type=int, default=5, help="c5: calibration queries also solved cold")
+    ap.add_argument("--c5-ic", choices=["trivalency", "wc"], default="trivalency",
+                    help="c5: IC probabilities (the configured trivalency, or weighted cascade)")
     ap.add_argument("--max-active", type=int, default=16, help="c5: queries in flight at most")
-    ap.add_argument("--hbm-budget-gib", type=int, default=160, help="c5: server memory budget")
-    ap.add_argument("--sequential", type=int, default=20, help="c5: queries also solved alone")
+    ap.add_argument("--hbm-budget-gib", type=int, default=200, help="c5: server memory budget")
     ap.add_argument("--c5-scale", type=int, default=24, help="c5: R-MAT scale of the graph")
     ap.add_argument("--instances", type=int, default=256, help="c4: instances of the mix")
     ap.add_argument("--autotune", type=int, default=0, metavar="SETS",
@@ -484,6 +588,8 @@ def main() -> int:
                          "(Barabasi-Albert n 1e6, r 2..32, k 50, eps 0.05)")
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--sweep-cpu-seconds", type=float, default=3.0)
+    ap.add_argument("--philox-peak", type=int, default=0, metavar="DRAWS",
+                    help="only run the Philox throughput probe (DRAWS per lane)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy kernel of BYTES (profiler counter scale)")
     args = ap.parse_args()
@@ -496,6 +602,14 @@ def main() -> int:
 
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 5)
+    if args.philox_peak:
+        import paper_2009_07325_amd as imm
+        imm.imm_init(0)
+        rates = [imm.imm_philox_rate(args.philox_peak) for _ in range(3)]
+        print(json.dumps({"probe": "philox4x32_10 draw + 4 ballots", "draws_per_lane": args.philox_peak,
+                          "gphilox_s": rates, "arithmetic_peak_gphilox_s": PEAK_GPHILOX,
+                          "frac_of_arithmetic_peak": max(rates) / PEAK_GPHILOX}), flush=True)
+        return 0
     if args.sweep:
         log("host:", json.dumps(host_info()))
         return bench_sweep(args)
@@ -571,21 +685,22 @@ def main() -> int:
         "generation_gphilox_s": gen_all,
     }
     if model == imm.IMM_LT:
-        # LT walks (k_rr_lt, both launch kinds): one step per member, whose algorithmic
-        # bytes are its vertex record, one cumulative threshold, one source, its id and
-        # its histogram entry; the walk is a chain of dependent loads (latency-bound)
+        # LT walks (k_lt_groups, plus k_rr_lt_hbm for walks past its lists): one step per
+        # member, whose algorithmic bytes are its vertex record, one cumulative threshold,
+        # one source, its id and its histogram entry; the walk is a chain of dependent
+        # loads (latency-bound)
         lt_bytes = sum(i["pool_ids"] for i in infos) * LT_STEP_BYTES
         lt_time = sum(i["t_rr_kernel_s"] + i["t_rr_heavy_s"] for i in infos)
         lt_launch = sum(i["rr_kernel_launches"] + i["rr_heavy_launches"] for i in infos)
         lt_gbs = lt_bytes / lt_time / 1e9 if lt_time > 0 else 0.0
         roofline = {
-            "kernel": "k_rr_lt",
+            "kernel": "k_lt_groups",
             "bound": "hbm",
             "achieved": lt_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": lt_gbs / HBM_PEAK_GBS,
-            "traffic": traffic_from_profile("k_rr_lt", args.workload),
+            "traffic": traffic_from_profile("k_lt_groups", args.workload),
             "avg_launch_ms": lt_time / max(lt_launch, 1) * 1e3,
             "bytes_per_launch": lt_bytes / max(lt_launch, 1),
             "steps_per_s": sum(i["pool_ids"] for i in infos) / lt_time if lt_time > 0 else 0.0,

@@ -74,7 +74,8 @@ typedef struct {
                                (imm_solve_pool: the pool's running total) */
     int64_t pool_ids;       /* total members over all generated sets (same convention) */
     int32_t phases;         /* greedy selections run (estimation phases + final) */
-    int32_t reserved;
+    int32_t heavy_redrawn;  /* IC sets of this solve's launches that outgrew a bounded heavy
+                               member list and were drawn again in a full one (huge graphs) */
     double lb;              /* lower bound LB of OPT from gIM Alg. 2 (1.0 if no phase passes) */
     double spread_est;      /* n * covered / |final sample|, the estimate of gIM Eq. 3 */
     double lambda_prime;
@@ -202,19 +203,27 @@ imm_status imm_solve_pool(imm_pool* p, int32_t k, double eps, double ell, int32_
                           void* stream, int32_t* seeds_out, imm_info* info);
 
 /* ---- autotuning ---------------------------------------------------------------------
- * Times the generation of RR sets [0, pilot_sets) of (g, model, seed) under each candidate
- * launch configuration (light-wave budget of 4-edge groups in {1024 .. 16384}, threads per
- * heavy set in {128, 256}) and keeps the fastest for pools created on g with that model
- * afterwards (imm_pool_create, imm_solve, servers; not batches).  RR sets, and therefore
- * every result, are identical under all configurations (gIM Sec. III-F sizes its blocks
- * for the same purpose).  The IMM_LIGHT_BUDGET / IMM_HEAVY_BLOCK environment variables
- * still override.  Not thread-safe with other calls on g. */
+ * Times the generation of RR sets [0, pilot_sets) of (g, model, seed) under candidate
+ * launch configurations and keeps the fastest for pools created on g with that model
+ * afterwards (imm_pool_create, imm_solve, servers; not batches).  The knobs, tuned one
+ * group at a time from the library defaults: IC light-wave budget of 4-edge groups
+ * {1024 .. 16384} x threads per heavy set {128, 256}; the on-chip list capacity (frontier
+ * capacity) of an IC light set {256, 512, 1024} or an LT walk {64, 128, 256}; the RR
+ * indices a wave takes per work-counter fetch (queue depth) {4, 8, 16, 32}.  RR sets, and
+ * therefore every result, are identical under all configurations (gIM Sec. III-F sizes its
+ * blocks for the same purpose).  The IMM_LIGHT_BUDGET / IMM_HEAVY_BLOCK / IMM_LIGHT_CAP /
+ * IMM_LT_LDS_CAP / IMM_FETCH environment variables still override.  Not thread-safe with
+ * other calls on g. */
 typedef struct {
     int64_t light_budget;
     int32_t heavy_block;
     int32_t candidates;           /* configurations timed */
     double best_sets_per_s;       /* pilot generation rate of the chosen configuration */
-    double default_sets_per_s;    /* ... of the library default (4096, 256) */
+    double default_sets_per_s;    /* ... of the library defaults */
+    int32_t light_cap;            /* chosen IC light-set list capacity */
+    int32_t lt_cap;               /* chosen LT walk list capacity */
+    int32_t fetch;                /* chosen RR indices per fetch */
+    int32_t reserved;
 } imm_tune_info;
 
 imm_status imm_autotune(imm_graph* g, imm_model model, uint64_t seed, int64_t pilot_sets,
@@ -256,6 +265,10 @@ typedef struct {
     int64_t rr_kernel_launches;
     double t_rr_heavy_s;
     int64_t rr_heavy_launches;
+    int64_t graph_ticks;        /* ticks whose selection half (per-item setup kernels and the
+                                   greedy launch) ran as one captured HIP graph: with
+                                   IMM_BATCH_GRAPH=1 (off by default, slower on the R-MAT
+                                   mix: capture costs more than the launches it saves) */
 } imm_batch_stats;
 
 imm_status imm_batch_solve(imm_batch_item* items, int32_t count, void* stream,
@@ -277,6 +290,9 @@ typedef struct {
     double throughput_qps;     /* completed / (last completion - first submission) */
     int64_t pool_sets_ic, pool_sets_lt;
     int64_t device_bytes;      /* pools + selection workspaces */
+    int64_t pool_resets;       /* pools emptied to give their memory to other queries (no
+                                  active query read them; their sets are drawn again,
+                                  identically, when needed) */
 } imm_server_stats;
 
 imm_status imm_server_create(const imm_graph* g, uint64_t seed_ic, uint64_t seed_lt,
@@ -349,6 +365,12 @@ double imm_mr_lambda_star(int64_t n, int64_t k, int32_t rounds, double eps, doub
 imm_status imm_spread_mc(const imm_graph* g, imm_model model, int32_t rounds, const int32_t* seeds,
                          int32_t nseeds, int64_t sims, uint64_t seed, uint32_t* per_sim_out,
                          int64_t* total_out, double* mean_out, double* stderr_out, void* stream);
+
+/* Measured peak of the IC generation roofline: Philox4x32-10 draws per second (in 1e9) of a
+ * loop that only draws and ballots the four words against a threshold, as the IC kernels
+ * do per 4 in-edges (8 waves per SIMD, two independent draws per lane, draws_per_lane in
+ * [2, 2^24]).  Synchronises the device's null stream.  Errors: IMM_EINVAL, IMM_EDEVICE. */
+imm_status imm_philox_rate(int64_t draws_per_lane, double* gphilox_s);
 
 /* IMM sample-size quantities, exposed for verification (IEEE double, no FMA contraction):
  * ln C(n,k); lambda' of the LB loop; lambda* of the final sample; ell' = ell(1+ln2/ln n). */

@@ -35,7 +35,8 @@ EXPORTS = ("imm_init", "imm_last_error", "imm_release_cached_memory", "imm_graph
            "imm_server_submit",
            "imm_server_poll", "imm_server_wait", "imm_server_stats_get", "imm_server_destroy",
            "imm_mr_pool_create", "imm_mrim_solve", "imm_mr_lambda_prime", "imm_mr_lambda_star",
-           "imm_spread_mc", "imm_select_seeds_noalloc", "imm_select_noalloc_bytes")
+           "imm_spread_mc", "imm_select_seeds_noalloc", "imm_select_noalloc_bytes",
+           "imm_philox_rate")
 
 
 class ImmError(RuntimeError):
@@ -53,7 +54,7 @@ class ImmInfo(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_int64), ("num_rr", ctypes.c_int64),
                 ("covered", ctypes.c_int64), ("edges_examined", ctypes.c_int64),
                 ("pool_ids", ctypes.c_int64), ("phases", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("lb", ctypes.c_double),
+                ("heavy_redrawn", ctypes.c_int32), ("lb", ctypes.c_double),
                 ("spread_est", ctypes.c_double), ("lambda_prime", ctypes.c_double),
                 ("lambda_star", ctypes.c_double), ("t_generate_s", ctypes.c_double),
                 ("t_select_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
@@ -68,7 +69,9 @@ class ImmInfo(ctypes.Structure):
 class ImmTuneInfo(ctypes.Structure):
     _fields_ = [("light_budget", ctypes.c_int64), ("heavy_block", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("best_sets_per_s", ctypes.c_double),
-                ("default_sets_per_s", ctypes.c_double)]
+                ("default_sets_per_s", ctypes.c_double), ("light_cap", ctypes.c_int32),
+                ("lt_cap", ctypes.c_int32), ("fetch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -87,7 +90,7 @@ class ImmBatchStats(ctypes.Structure):
                 ("t_generate_s", ctypes.c_double), ("t_select_s", ctypes.c_double),
                 ("t_total_s", ctypes.c_double), ("t_rr_kernel_s", ctypes.c_double),
                 ("rr_kernel_launches", ctypes.c_int64), ("t_rr_heavy_s", ctypes.c_double),
-                ("rr_heavy_launches", ctypes.c_int64)]
+                ("rr_heavy_launches", ctypes.c_int64), ("graph_ticks", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -100,7 +103,8 @@ class ImmServerStats(ctypes.Structure):
                 ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
                 ("mean_latency_s", ctypes.c_double), ("max_latency_s", ctypes.c_double),
                 ("throughput_qps", ctypes.c_double), ("pool_sets_ic", ctypes.c_int64),
-                ("pool_sets_lt", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("pool_sets_lt", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("pool_resets", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -135,6 +139,7 @@ def lib() -> ctypes.CDLL:
             "imm_rr_histogram": [p, i64, i64, p],
             "imm_select_seeds": [p, i64, i64, i32, p, p, p],
             "imm_select_seeds_noalloc": [p, i64, i64, i32, p, p, p],
+            "imm_philox_rate": [i64, ctypes.POINTER(ctypes.c_double)],
             "imm_solve": [p, i32, dbl, dbl, ctypes.c_int, ctypes.POINTER(ImmOptions), p,
                           ctypes.POINTER(ImmInfo)],
             "imm_solve_pool": [p, i32, dbl, dbl, i32, p, p, ctypes.POINTER(ImmInfo)],
@@ -300,6 +305,13 @@ def imm_select_seeds_noalloc(p, first: int, count: int, k: int, stream=None,
     _check(lib().imm_select_seeds_noalloc(p, first, count, k, _ptr(seeds), ctypes.byref(cov),
                                           _stream(stream)))
     return seeds, cov.value
+
+
+def imm_philox_rate(draws_per_lane: int = 16384) -> float:
+    """Measured Philox4x32-10 draws per second (1e9) of a draw-and-ballot loop."""
+    out = ctypes.c_double()
+    _check(lib().imm_philox_rate(draws_per_lane, ctypes.byref(out)))
+    return out.value
 
 
 def imm_select_noalloc_bytes(p, first: int, count: int, k: int) -> int:

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libimm.so")
-SOURCES = ["api.cpp", "devmem.cpp", "generate.cpp", "batch.cpp", "tune.cpp", "serve.cpp", "mrim.cpp", "spread.cpp", "graph.hip", "rr_gen.hip", "select.hip", "mr_sets.hip", "fwd_mc.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "devmem.cpp", "generate.cpp", "batch.cpp", "tune.cpp", "serve.cpp", "mrim.cpp", "spread.cpp", "graph.hip", "rr_gen.hip", "select.hip", "mr_sets.hip", "fwd_mc.hip", "noalloc.hip", "probe.hip"]
 ARCH = os.environ.get("IMM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

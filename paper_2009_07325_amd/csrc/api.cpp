@@ -518,6 +518,7 @@ void SelectWs::release() {
     dfree(seeds);
     dfree(n_covered);
     hfree(host_seeds);
+    hfree(host_keys);
     hfree(host_cov);
     dfree(hot_bits);
     dfree(cnt_hist);
@@ -530,6 +531,7 @@ void SelectLaunch::release() {
     dfree(d_inst);
     dfree(bar);
     hfree(host_bar);
+    hfree(host_inst);
     cap = 0;
 }
 
@@ -560,9 +562,11 @@ static imm_status ensure_select(imm_pool* p, SelectWs* w, int64_t count, int32_t
         dfree(w->keys);
         dfree(w->seeds);
         hfree(w->host_seeds);
+        hfree(w->host_keys);
         IMM_TRY(dalloc(&w->keys, k));
         IMM_TRY(dalloc(&w->seeds, k));
         IMM_TRY(halloc(&w->host_seeds, k));
+        IMM_TRY(halloc(&w->host_keys, k));
         w->cap_k = k;
     }
     return IMM_OK;
@@ -697,14 +701,28 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
 
 imm_status imm::select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,
                            hipStream_t s) {
+    IMM_TRY(select_enqueue(L, ws, inst, ninst, s));
+    return select_wait(L, s);
+}
+
+imm_status imm::select_enqueue(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst,
+                               int32_t ninst, hipStream_t s, bool captured) {
     if (ninst > L->cap) {
         L->release();
         IMM_TRY(dalloc(&L->d_inst, ninst));
         IMM_TRY(dalloc(&L->bar, 1));
         IMM_TRY(halloc(&L->host_bar, 1));
+        IMM_TRY(halloc(&L->host_inst, ninst));
         L->cap = ninst;
     }
-    HIP_TRY(hipMemcpyAsync(L->d_inst, inst, sizeof(SelInst) * (size_t)ninst, hipMemcpyHostToDevice, s));
+    // a captured copy reads its source when the graph runs: stage the descriptors in
+    // pinned memory owned by the launch
+    const SelInst* src = inst;
+    if (L->host_inst) {
+        memcpy(L->host_inst, inst, sizeof(SelInst) * (size_t)ninst);
+        src = L->host_inst;
+    }
+    HIP_TRY(hipMemcpyAsync(L->d_inst, src, sizeof(SelInst) * (size_t)ninst, hipMemcpyHostToDevice, s));
     // one cooperative launch per group of at most select_max_inst() instances; the barrier
     // counters start from zero for each launch, and its error flag is collected at the end
     const int32_t per = select_max_inst();
@@ -714,16 +732,23 @@ imm_status imm::select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* 
         int32_t maxk = 0;
         for (int32_t i = a; i < a + cnt; ++i) maxk = std::max(maxk, inst[i].k);
         if (a > 0) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(L->bar), 16 * 16 + 1, 0u, s));
-        HIP_TRY(launch_select_coop(L->d_inst + a, cnt, maxk, L->bar, s));
+        HIP_TRY(launch_select_coop(L->d_inst + a, cnt, maxk, L->bar, s, captured));
     }
     HIP_TRY(hipMemcpyAsync(L->host_bar, L->bar, sizeof(GridBarrier), hipMemcpyDeviceToHost, s));
     for (int32_t i = 0; i < ninst; ++i) {
         SelectWs* w = ws[i];
         HIP_TRY(hipMemcpyAsync(w->host_seeds, w->seeds, sizeof(int32_t) * (size_t)w->k,
                                hipMemcpyDeviceToHost, s));
+        if (w->host_keys)
+            HIP_TRY(hipMemcpyAsync(w->host_keys, w->keys, sizeof(unsigned long long) * (size_t)w->k,
+                                   hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(w->host_cov, w->n_covered, sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, s));
     }
+    return IMM_OK;
+}
+
+imm_status imm::select_wait(SelectLaunch* L, hipStream_t s) {
     HIP_TRY(hipStreamSynchronize(s));
     if (L->host_bar->err) return fail(IMM_EDEVICE, "selection grid barrier timed out");
     return IMM_OK;
@@ -760,6 +785,7 @@ imm_status imm::run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_t 
     double t_gen = 0.0, t_sel = 0.0;
     const double kernel_s0 = p->gen.kernel_s, heavy_s0 = p->gen.heavy_s;
     const int64_t launches0 = p->gen.kernel_launches, heavy0 = p->gen.heavy_launches;
+    const int64_t redrawn0 = p->gen.heavy_overflow;
     if (p->rounds > 1 && fresh) return fail(IMM_EINVAL, "multi-round solves reuse the estimation sets");
     ImmPlan plan;
     IMM_TRY(plan.init(pool_vertices(p), k, eps, ell, fresh, p->rounds));
@@ -785,6 +811,7 @@ imm_status imm::run_imm(imm_pool* p, int32_t k, double eps, double ell, int32_t 
         info->covered = plan.covered;
         info->edges_examined = (int64_t)(p->sum.edges + p->sum.hedges);
         info->edges_heavy = (int64_t)p->sum.hedges;
+        info->heavy_redrawn = (int32_t)std::min<int64_t>(p->gen.heavy_overflow - redrawn0, INT32_MAX);
         info->pool_ids = (int64_t)p->sum.placed;
         info->phases = plan.phases;
         info->lb = plan.lb;

@@ -174,8 +174,16 @@ __global__ void k_build_lrec(int64_t m, const uint32_t* __restrict__ cum, const 
     }
 }
 
-// One wave per vertex: the guide entry of each of its 2d buckets by a binary search over
-// its thresholds (the last is saturated, so a qualifying edge always exists).
+// One wave per vertex, lanes over its in-edges.  The guide of bucket b is the first edge j
+// with cum_j > L_b (a saturated threshold counts as 2^32), i.e. the edge with
+// cum_{j-1} <= L_b < cum_j, so edge j is the guide of exactly the buckets whose lower end
+// lies in [cum_{j-1}, cum_j): b in [first(cum_{j-1}), first(cum_j)), where first(c), the
+// smallest b with L_b >= c, is 0 for c = 0 and floor((c - 1) 2d / 2^32) + 1 otherwise
+// (ceil(y) >= c iff y > c - 1).  Each edge writes its own buckets: O(d) per vertex.
+__device__ __forceinline__ uint64_t first_bucket(uint64_t c, uint64_t nb) {
+    return c == 0 ? 0 : (((c - 1) * nb) >> 32) + 1;
+}
+
 __global__ void k_build_guide(int32_t n, const VRec* __restrict__ vrec, const uint32_t* __restrict__ cum,
                               const LtRec* __restrict__ lrec, LtRec* __restrict__ grec,
                               uint32_t* __restrict__ gidx) {
@@ -186,16 +194,22 @@ __global__ void k_build_guide(int32_t n, const VRec* __restrict__ vrec, const ui
         const int64_t s = vrec[v].start;
         const uint32_t d = vrec[v].deg & kDegMask;
         const uint64_t nb = 2ull * d;
-        for (uint64_t b = lane; b < nb; b += kWave) {
-            const uint64_t lb = ((b << 32) + nb - 1) / nb;        // ceil(b 2^32 / 2d)
-            uint32_t lo = 0, hi = d - 1;                          // first qualifying in [lo, hi]
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                const uint32_t c = cum[s + mid];
-                if (c == kAlways || (uint64_t)c > lb) hi = mid; else lo = mid + 1;
+        for (uint32_t j = lane; j < d; j += kWave) {
+            const uint32_t cj = cum[s + j];
+            const uint64_t hi_c = cj == kAlways ? (1ull << 32) : (uint64_t)cj;
+            uint64_t lo_c = 0;
+            if (j > 0) {
+                const uint32_t cp = cum[s + j - 1];
+                lo_c = cp == kAlways ? (1ull << 32) : (uint64_t)cp;
             }
-            grec[2 * s + (int64_t)b] = lrec[s + lo];
-            gidx[2 * s + (int64_t)b] = lo;
+            const uint64_t b_lo = first_bucket(lo_c, nb);
+            const uint64_t b_hi = min(first_bucket(hi_c, nb), nb);
+            if (b_lo >= b_hi) continue;
+            const LtRec rec = lrec[s + j];
+            for (uint64_t b = b_lo; b < b_hi; ++b) {
+                grec[2 * s + (int64_t)b] = rec;
+                gidx[2 * s + (int64_t)b] = j;
+            }
         }
     }
 }

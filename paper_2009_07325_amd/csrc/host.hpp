@@ -178,6 +178,9 @@ namespace imm {
 struct GenTuning {
     int64_t budget = 0;
     int heavy_block = 0;
+    int light_cap = 0;      // IC: on-chip members of a light set (frontier capacity)
+    int lt_cap = 0;         // LT: on-chip members of a first-pass walk
+    int fetch = 0;          // RR indices per work-counter fetch (queue depth)
 };
 }  // namespace imm
 
@@ -236,6 +239,8 @@ struct SelectWs {
     int32_t* seeds = nullptr;
     unsigned long long* n_covered = nullptr;
     int32_t* host_seeds = nullptr;            // pinned, cap_k
+    unsigned long long* host_keys = nullptr;  // pinned, cap_k: each round's argmax key
+                                              // (gain + 1 in the high word; 0: not run)
     unsigned long long* host_cov = nullptr;   // pinned
     int32_t k = 0;                            // of the prepared selection
     // hot set of single-instance selections (select.hip)
@@ -256,6 +261,7 @@ struct SelectLaunch {
     SelInst* d_inst = nullptr;
     GridBarrier* bar = nullptr;
     GridBarrier* host_bar = nullptr;          // pinned
+    SelInst* host_inst = nullptr;             // pinned staging of the descriptors, or null
     void release();
 };
 
@@ -270,15 +276,20 @@ struct GenCtx {
     int64_t vis_words = 0;
     uint32_t* visited = nullptr;        // grid * 4 light bitmaps
     int64_t hslots = 0;                 // heavy slots (IC: workgroups, LT: waves)
-    uint32_t* hvisited = nullptr;
-    int32_t* hlist = nullptr;           // hslots lists of vis_n entries
+    uint32_t* hvisited = nullptr;       // hslots bitmaps
+    int32_t* hlist = nullptr;           // member lists: LT hslots x vis_n entries; IC
+    int64_t hlist_words = 0;            // hlist_words entries shared by a launch's slots
+    unsigned long long* over = nullptr; // IC heavy sets that outgrew their list (cap_queue)
     int64_t budget = 4096;              // light-wave group budget per set
     int heavy_block = 256;              // threads per heavy set (64, 128, 256 or 1024)
     int64_t heavy_scratch = (int64_t)16 << 30;   // bytes of heavy bitmaps + lists at most
+    int64_t heavy_list = 0;             // IC heavy list entries per slot (0: chosen per launch)
     int32_t* lt_ext = nullptr;          // LT first pass: extension lists of the grid's walk slots
     int64_t lt_ext_words = 0;
     int lt_lds_cap = kLtLdsCap;         // members a first-pass walk keeps in LDS / extension
     int lt_ext_cap = kLtExtCap;
+    int light_cap = 1024;               // IC light set's on-chip list (frontier capacity)
+    int fetch = kGenFetch;              // RR indices per work fetch (queue depth)
 
     LaunchCounters* lc = nullptr;
     LaunchCounters* host_lc = nullptr;  // pinned
@@ -300,13 +311,17 @@ struct GenCtx {
     int64_t kernel_launches = 0;
     double heavy_s = 0.0;               // heavy kernel (IC) / HBM-list walk kernel (LT)
     int64_t heavy_launches = 0;
+    int64_t heavy_overflow = 0;         // IC heavy sets drawn again in full lists
 
     // Defaults, then `tuning` (if given and set), then the IMM_LIGHT_BUDGET /
-    // IMM_HEAVY_BLOCK / IMM_HEAVY_SCRATCH_GIB / IMM_LT_LDS_CAP / IMM_LT_EXT_CAP environment
-    // overrides.
+    // IMM_HEAVY_BLOCK / IMM_LIGHT_CAP / IMM_FETCH / IMM_HEAVY_SCRATCH_GIB / IMM_HEAVY_LIST /
+    // IMM_LT_LDS_CAP / IMM_LT_EXT_CAP environment overrides.
     imm_status init(int device_, imm_model model_, int cus_, const GenTuning* tuning = nullptr);
     imm_status ready();
     int64_t bytes() const;
+    // Device bytes of the heavy scratch that the first IC heavy launch on graphs of up to n
+    // vertices allocates (0 once allocated, and for LT).
+    int64_t heavy_bytes(int64_t n) const;
     void release();
 };
 
@@ -382,5 +397,11 @@ int32_t select_hot_max(int64_t n);
 // instance's seeds and covered count to its workspace's pinned buffers (synchronises s).
 imm_status select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,
                       hipStream_t s);
+// select_run in two halves: enqueue (descriptors, barrier reset, launch, read-backs; no
+// synchronisation, so it may be captured into a graph: captured launches use an ordinary
+// launch of the same grid) and wait (synchronises s, reports a barrier timeout).
+imm_status select_enqueue(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,
+                          hipStream_t s, bool captured = false);
+imm_status select_wait(SelectLaunch* L, hipStream_t s);
 
 }  // namespace imm

@@ -13,7 +13,8 @@ namespace imm {
 struct alignas(64) PoolCounters {
     unsigned long long tail;       // next free entry of the id buffer (chunk reservations)
     unsigned int n_capacity;       // sets that found the id buffer full (this launch)
-    unsigned int pad[13];
+    unsigned int max_len;          // largest set the heavy kernel placed (all launches)
+    unsigned int pad[12];
     unsigned long long placed[64]; // members written
     unsigned long long edges[64];  // in-edges examined by sets placed by the light kernel
     unsigned long long hedges[64]; // ... by the heavy kernel
@@ -25,17 +26,19 @@ struct alignas(64) LaunchCounters {
     unsigned int hwork;            // heavy work-queue cursor
     unsigned int n_heavy;          // sets the light launch queued for the heavy launch
     unsigned long long arena;      // handoff arena words in use
-    unsigned int pad[10];
+    unsigned int n_over;           // IC heavy sets that outgrew their slot's member list
+    unsigned int pad[9];
 };
 
 // Host-bound summary of one pool's counters, written by launch_pool_summary.
 struct PoolSummary {
     unsigned long long tail, placed, edges, hedges;
     unsigned int n_capacity;       // read and then cleared for the next launch
-    unsigned int pad;
+    unsigned int max_len;
 };
 
-constexpr int kGenFetch = 8;       // RR indices a light wave takes per work-counter fetch
+constexpr int kGenFetch = 8;       // RR indices a wave takes per work-counter fetch (default)
+constexpr int kGenFetchMax = 64;   // ... at most
 constexpr int kGenIdChunk = 1024;  // id-buffer entries a light wave reserves at a time
 
 // ---- graph.hip ----------------------------------------------------------------------
@@ -100,6 +103,10 @@ struct GenLaunch {
     int32_t* arena;
     int64_t arena_cap;
     uint32_t n_queue;        // IC heavy launch: entries of heavy_list to process
+    // IC heavy launch: sets whose members outgrow list_stride are dropped (their bitmap
+    // bits cleared) and their queue entries appended here (count in lc->n_over), to be
+    // drawn again from the root in slots of a full list; nullptr: list_stride holds any set
+    unsigned long long* over_list;
     // LT walk over HBM lists: when set, the work items are heavy_in[0, total) (entries as
     // in heavy_list) instead of the instances' RR ranges
     const unsigned long long* heavy_in;
@@ -114,6 +121,8 @@ struct GenLaunch {
     int32_t* lt_ext;
     int32_t lt_lds_cap;
     int32_t lt_ext_cap;
+    int32_t light_cap;       // IC light kernel: members a set may hold on chip (<= 1024)
+    int32_t fetch;           // RR indices a wave takes per work-counter fetch (queue depth)
 };
 
 constexpr int kLtLdsCap = 256;           // LDS entries per walk of the first LT pass
@@ -190,8 +199,9 @@ struct SelInst {
     unsigned long long* n_covered; // zeroed
     // Estimation phases: the smallest coverage that passes the phase's test.  Greedy gains
     // never increase, so once (covered so far) + (rounds left) x (this round's gain) falls
-    // below it the phase fails whatever the remaining seeds are, and the instance stops.
-    // 0: always run all k rounds.
+    // below it the phase fails whatever the remaining seeds are, and the instance stops;
+    // n_covered then receives that bound (below need: an upper bound of the coverage all
+    // k rounds would have reached).  0: always run all k rounds.
     int64_t need;
     // A single-instance launch may read its index as segments: the entries of v are those
     // of every segment j, seg_inv[j][seg_off[j][v] .. seg_off[j][v + 1]).  nseg == 1 means
@@ -230,8 +240,9 @@ struct alignas(64) GridBarrier {
 };
 int select_coop_grid();            // blocks of the cooperative launch (co-resident)
 int select_max_inst();             // instances one cooperative launch can take
+// plain: an ordinary launch of the same grid (stream capture, some profilers)
 hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
-                              hipStream_t s);
+                              hipStream_t s, bool plain = false);
 // ---- mr_sets.hip -----------------------------------------------------------------------
 // The round pools of a multi-round pool (gIM Sec. IV-H): round t's sets, read by the merge.
 struct MrSrc {

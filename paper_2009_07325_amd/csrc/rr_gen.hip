@@ -33,7 +33,6 @@ namespace imm {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLightCap = 1024;    // members a light set may hold on chip
-constexpr int kFetch = kGenFetch;
 constexpr int kIdChunk = kGenIdChunk;
 
 int rr_light_capacity() { return kLightCap; }
@@ -97,11 +96,11 @@ __device__ __forceinline__ bool next_set(const GenLaunch& L, WaveState& ws, int3
                                          uint32_t& r) {
     if (ws.left == 0) {
         unsigned long long i = 0;
-        if (lane_id() == 0) i = atomic_add_agent(&L.lc->work, (unsigned long long)kFetch);
+        if (lane_id() == 0) i = atomic_add_agent(&L.lc->work, (unsigned long long)L.fetch);
         i = uniform64(i);
         if ((int64_t)i >= L.total) return false;
         ws.cur = (int64_t)i;
-        ws.left = (int32_t)min((int64_t)kFetch, L.total - (int64_t)i);
+        ws.left = (int32_t)min((int64_t)L.fetch, L.total - (int64_t)i);
     }
     const int64_t w = ws.cur++;
     --ws.left;
@@ -358,7 +357,7 @@ __device__ __forceinline__ bool resolve_staged(const GraphView& a, const uint32_
 // overflow the set is abandoned (and the bits of the vertices not appended are cleared).
 __device__ __forceinline__ void flush_light(const GraphView& a, uint32_t* stage, int32_t& n,
                                             int32_t* list, int32_t& size, bool& abandon,
-                                            uint32_t* vis) {
+                                            uint32_t* vis, int32_t cap) {
     wave_sync();
     for (int32_t i0 = 0; i0 < n; i0 += kWave) {
         int32_t u = 0;
@@ -366,7 +365,7 @@ __device__ __forceinline__ void flush_light(const GraphView& a, uint32_t* stage,
         const uint64_t m = ballot(fresh);
         const int32_t c = (int32_t)__popcll(m);
         if (c == 0) continue;
-        if (abandon || size + c > kLightCap) {
+        if (abandon || size + c > cap) {
             abandon = true;
             if (fresh) vis_clear(vis, u);
             continue;
@@ -399,9 +398,12 @@ __device__ __forceinline__ void ring_put(RecRing& ring, int32_t p, const VRec& r
 // Heavy kernel: appends to the workgroup's HBM list (positions from an LDS counter) and
 // puts each new member's vertex record in the ring.  The record is loaded for every
 // resolved edge, in parallel with its test-and-set, so the two waits overlap.
+// kBounded: members past `cap` are not stored (their bits are cleared again): the set has
+// outgrown its list and is dropped at the end of the batch.
+template <bool kBounded>
 __device__ __forceinline__ void flush_block(const GraphView& a, uint32_t* stage, int32_t& n,
                                             int32_t* list, int32_t* s_size, uint32_t* vis,
-                                            RecRing& ring) {
+                                            RecRing& ring, int32_t cap) {
     wave_sync();
     for (int32_t i0 = 0; i0 < n; i0 += kWave) {
         const int32_t i = i0 + lane_id();
@@ -421,8 +423,12 @@ __device__ __forceinline__ void flush_block(const GraphView& a, uint32_t* stage,
         at = __shfl(at, 0, kWave);
         if (fresh) {
             const int32_t p = at + (int32_t)lanes_below(m);
-            list[p] = u;
-            ring_put(ring, p, rec);
+            if (!kBounded || p < cap) {
+                list[p] = u;
+                ring_put(ring, p, rec);
+            } else {
+                vis_clear(vis, u);
+            }
         }
     }
     n = 0;
@@ -508,7 +514,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             examined += level_edges;
 
             int32_t nst = 0;
-            auto flush = [&]() { flush_light(a, L.stage, nst, list, size, abandon, vis); };
+            auto flush = [&]() { flush_light(a, L.stage, nst, list, size, abandon, vis, G.light_cap); };
             // big vertices: one at a time, wave-uniform vertex data
             uint64_t bigmask = ballot(big);
             while (bigmask && !abandon) {
@@ -602,7 +608,9 @@ __device__ __forceinline__ uint64_t block_incl_scan(uint64_t v, uint64_t* wsum) 
 // vertex, its small-group prefix, its index among the big vertices and its first chunk,
 // packed in one 64-bit value (fields of 16, 16 and 32 bits: a batch has at most 1024
 // vertices, each with fewer than kWave groups in the first field).
-template <int kHeavyBlock>
+// kBounded: member lists of list_stride entries that a set may outgrow (G.over_list);
+// otherwise lists hold any set.
+template <int kHeavyBlock, bool kBounded>
 __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ic_heavy(GenLaunch G) {
     constexpr int kHeavyWaves = kHeavyBlock / kWave;
     __shared__ int32_t pre[kHeavyBlock + 1];
@@ -720,7 +728,9 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
             const uint32_t nchunks = uniform(s_nchunks);
             const int32_t total_small = uniform(pre[nb]);
             int32_t nst = 0;
-            auto flush = [&]() { flush_block(a, stage, nst, list, &s_size, vis, ring); };
+            auto flush = [&]() {
+                flush_block<kBounded>(a, stage, nst, list, &s_size, vis, ring, (int32_t)G.list_stride);
+            };
             // big vertices: chunk c -> the vertex k with bcp[k] <= c < bcp[k + 1]; a wave's
             // chunks increase, so its vertex index only moves forward
             uint32_t k = ~0u, c_lo = 0, c_hi = 0;   // chunks [c_lo, c_hi) are vertex k's
@@ -806,6 +816,25 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
             head += nb;
             size = s_size;
             __syncthreads();
+            if (kBounded && size > G.list_stride) size = head;   // outgrown: the traversal ends
+        }
+        if (kBounded && s_size > G.list_stride) {
+            // outgrew the list (flush_block stored list_stride members and cleared the bits
+            // of the rest): the queue entry goes to the full-list pass, which draws the set
+            // again from its root, and the stored members' bits are cleared.  (A full list
+            // holds any set; without an overflow list this would be a capacity miss.)
+            if (tid == 0) {
+                if (G.over_list) {
+                    const unsigned int o = atomic_add_agent(&G.lc->n_over, 1u);
+                    G.over_list[o] = G.heavy_list[s_idx];   // this set's queue entry
+                } else {
+                    push_capacity_miss(I, r);
+                }
+            }
+            for (int32_t i = tid; i < (int32_t)G.list_stride; i += kHeavyBlock) vis_clear(vis, list[i]);
+            vis_fence();
+            __syncthreads();
+            continue;
         }
         // place the set
         if (tid == 0) {
@@ -819,6 +848,8 @@ __global__ __launch_bounds__(kHeavyBlock) __attribute__((amdgpu_waves_per_eu(8))
                 global(I.rr_len)[r] = size;
                 atomic_add_agent(&c->placed[slot & 63], (unsigned long long)size);
                 atomic_add_agent(&c->hedges[slot & 63], (unsigned long long)examined);
+                __hip_atomic_fetch_max(&c->max_len, (unsigned int)size, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 if (s_light) atomic_add_agent(&c->edges[slot & 63], s_light);
             }
             s_base = b;
@@ -1106,15 +1137,20 @@ hipError_t launch_ic_light(const GenLaunch& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s) {
+template <bool kBounded>
+hipError_t launch_ic_heavy_t(const GenLaunch& a, int block, int grid, hipStream_t s) {
     switch (block) {
-        case 64: k_ic_heavy<64><<<grid, 64, 0, s>>>(a); break;
-        case 128: k_ic_heavy<128><<<grid, 128, 0, s>>>(a); break;
-        case 256: k_ic_heavy<256><<<grid, 256, 0, s>>>(a); break;
-        case 1024: k_ic_heavy<1024><<<grid, 1024, 0, s>>>(a); break;
+        case 64: k_ic_heavy<64, kBounded><<<grid, 64, 0, s>>>(a); break;
+        case 128: k_ic_heavy<128, kBounded><<<grid, 128, 0, s>>>(a); break;
+        case 256: k_ic_heavy<256, kBounded><<<grid, 256, 0, s>>>(a); break;
+        case 1024: k_ic_heavy<1024, kBounded><<<grid, 1024, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_ic_heavy(const GenLaunch& a, int block, int grid, hipStream_t s) {
+    return a.over_list ? launch_ic_heavy_t<true>(a, block, grid, s) : launch_ic_heavy_t<false>(a, block, grid, s);
 }
 
 hipError_t launch_lt(const GenLaunch& a, bool big, int grid, hipStream_t s) {
@@ -1130,10 +1166,10 @@ int gen_blocks_per_cu(int which) {
     hipError_t e = hipSuccess;
     switch (which) {
         case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_light, kBlock, 0); break;
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<1024>, 1024, 0); break;
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<256>, 256, 0); break;
-        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<128>, 128, 0); break;
-        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<64>, 64, 0); break;
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<1024, true>, 1024, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<256, true>, 256, 0); break;
+        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<128, true>, 128, 0); break;
+        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ic_heavy<64, true>, 64, 0); break;
         case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lt_groups, kBlock, 0); break;
         default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rr_lt_hbm, kBlock, 0); break;
     }
@@ -1158,7 +1194,7 @@ __global__ void k_pool_summary(const GenInst* __restrict__ inst, int32_t ninst,
         o.edges = ed;
         o.hedges = he;
         o.n_capacity = c->n_capacity;
-        o.pad = 0;
+        o.max_len = c->max_len;
         out[i] = o;
         c->n_capacity = 0u;
     }

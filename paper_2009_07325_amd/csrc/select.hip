@@ -258,8 +258,13 @@ __device__ __forceinline__ void st_co(IMM_GLOBAL T* p, T v) {
 // the barrier is visible to coherent (agent-scope) loads issued after it.  Data shared
 // between blocks inside the kernel is only read and written with such loads, stores and
 // atomics, so no cache write-back or invalidate is needed.  Counters are monotonic
-// (epoch-based) and spread over 16 lines; a wait that exceeds ~2^24 polls sets bar->err
-// and every block leaves, so no wave spins forever.
+// (epoch-based) and spread over 16 lines; a wait longer than kBarrierTimeout sets
+// bar->err and every block leaves, so no wave spins forever.  The bound is a time, not a
+// poll count: a cover step of many instances over RR sets of 10^5 members (trivalency IC
+// on R-MAT scale 24) legitimately keeps some blocks busy for seconds, past the few
+// seconds that 2^24 polls had allowed.
+constexpr uint64_t kBarrierTimeout = 100000000ull * 120;   // s_memrealtime ticks (100 MHz): 120 s
+
 __device__ __forceinline__ bool grid_sync(GridBarrier* bar, unsigned int& epoch) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -277,8 +282,10 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* bar, unsigned int& epoch)
         const unsigned int target = (epoch + 1) * ngroups;
         int ok = 1;
         unsigned int polls = 0;
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
         while (ld_co(&bar->top) < target) {
-            if (++polls > (1u << 24) || ld_co(&bar->err)) {
+            if ((++polls & 63u) == 0u &&
+                (ld_co(&bar->err) || __builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeout)) {
                 st_co(&bar->err, 1u);
                 ok = 0;
                 break;
@@ -442,7 +449,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restri
     __shared__ int64_t pre[kCoopBlock + 1];
     __shared__ int64_t wsum[kCoopWaves];
     __shared__ int32_t s_thr;
-    const int tid = threadIdx.x, lane = lane_id();
+    const int tid = threadIdx.x;
     // thread t holds buckets kHotBuckets - 1 - (4t + j), j = 0..3 (descending)
     uint32_t cj[4];
     int64_t local = 0;
@@ -767,10 +774,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         if (tid < ninst && round < inst[tid].k && !S.stopped[tid]) {
             const SelInst& I = inst[tid];
             const unsigned long long key = solo ? S.key : ld_co(global(I.keys) + round);
+            if (solo && blockIdx.x == 0) st_co(global(I.keys) + round, key);   // round's gain, for the caller
             const int64_t gain = key ? (int64_t)(key >> 32) - 1 : 0;
             const int64_t bound = cov_before + (int64_t)(I.k - round) * gain;
             if (I.need > 0 && bound < I.need) {
                 S.stopped[tid] = 1;
+                // the coverage all k rounds could reach at most (still below need): what
+                // the caller reads as this failed phase's coverage
+                if (blockIdx.x == 0) st_co(global(I.n_covered), (unsigned long long)bound);
             } else {
                 live = true;
                 const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
@@ -904,13 +915,13 @@ static bool plain_launch() {
 }
 
 hipError_t launch_select_coop(const SelInst* inst, int32_t ninst, int32_t maxk, GridBarrier* bar,
-                              hipStream_t s) {
+                              hipStream_t s, bool plain) {
     if (ninst < 1 || ninst > kMaxInst) return hipErrorInvalidValue;
     const int grid = select_coop_grid();
     const int capacity = select_coop_capacity();
     if (capacity < 1 || grid > capacity) return hipErrorCooperativeLaunchTooLarge;
     if (grid > kMaxCoopGrid) return hipErrorInvalidValue;
-    if (plain_launch()) {
+    if (plain || plain_launch()) {
         k_select_coop<<<grid, kCoopBlock, 0, s>>>(inst, ninst, maxk, bar);
         return hipGetLastError();
     }

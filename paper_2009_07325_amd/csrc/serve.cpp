@@ -20,6 +20,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -58,7 +59,8 @@ struct Result {
 
 struct imm_server {
     const imm_graph* g = nullptr;
-    imm_pool* pools[2] = {nullptr, nullptr};   // IC, LT
+    imm_pool* pools[2] = {nullptr, nullptr};   // IC, LT (worker thread only after creation)
+    uint64_t seeds[2] = {0, 0};
     int64_t budget = 0;
     int32_t max_active = 0;
     hipStream_t stream = nullptr;
@@ -78,6 +80,7 @@ struct imm_server {
 
     // statistics (under mu)
     int64_t submitted = 0, completed = 0, rejected = 0, ticks = 0;
+    std::atomic<int64_t> pool_resets{0};
     double t_first_submit = -1.0, t_last_done = 0.0;
     std::vector<double> latencies;
     imm_status worker_status = IMM_OK;
@@ -86,6 +89,15 @@ struct imm_server {
     std::atomic<int64_t> bytes_snapshot{0};                      // device_bytes() after a tick
     std::atomic<double> mean_members[2] = {{16.0}, {16.0}};   // per pool, after each generation
     std::atomic<int64_t> pool_sets[2] = {{0}, {0}};
+    bool trace = false;                                        // IMM_SERVE_TRACE=1: a line per tick
+    bool frugal = false;       // IMM_SERVE_FRUGAL=1: drop every pool no query reads after each tick
+    // coverage seen per pool (worker thread only): for recent selections, the fraction of
+    // their sets covered after each greedy round they ran, and their number of sets
+    struct Seen {
+        std::vector<double> cum;
+        int64_t sets;
+    };
+    std::vector<Seen> cov_seen[2];
 
     int64_t device_bytes() const {
         int64_t b = 0;
@@ -119,15 +131,108 @@ int64_t query_bytes(const imm_server* S, const Query& q, bool minimal) {
 // buffer grows by doubling, so up to twice that) plus the step's selection workspace.  A
 // query whose step needs more than the whole budget can never run and is rejected with
 // IMM_ECAPACITY before its pool grows (gIM Alg. 2 / Alg. 1 sample sizes grow without
-// bound as eps shrinks, while device memory does not).
-double step_bytes(const imm_server* S, const Query& q) {
+// bound as eps shrinks, while device memory does not).  The final selection reads at least
+// theta = lambda* / LB >= lambda* / n sets (LB = n F_R(S) / (1 + eps') never exceeds n),
+// so every step is charged for at least that many: a query that cannot reach its final
+// selection is rejected at its first step instead of after its estimation phases.
+double bytes_for(const imm_server* S, const Query& q, double sets, double sel) {
     const double n = (double)S->g->n;
     const double mean = S->mean_members[q.model].load();
-    const double sets = (double)q.gen_upto;
-    const double pool = sets * 12.0 + 2.0 * sets * mean * 4.0;
-    const double sel = (double)q.sel_count;
+    const imm_pool* p = S->pools[q.model];
+    // generation scratch: what the pool's context holds, and the heavy scratch its first
+    // heavy launch allocates
+    const double gen = (double)p->gen.bytes() + (double)p->gen.heavy_bytes(S->g->n);
+    const double pool = sets * 12.0 + 2.0 * sets * mean * 4.0 + n * 4.0 + gen;
     const double ws = n * 20.0 + sel * mean * 4.0 + sel * 4.0;
     return pool + ws;
+}
+
+// Upper bound on the coverage fraction that a query's k greedy seeds reach in its passing
+// estimation phase, from the selections already run on its pool.  A selection that ran r
+// rounds gives the coverage after each j <= r seeds; past r, greedy gains never increase,
+// so k seeds cover at most the coverage after r plus (k - r) times round r's gain.  The
+// fraction greedy reaches shrinks, if anything, as the sample grows (it fits a small sample
+// better), so only selections over no more sets than the query's first phase reads are
+// used.  The bound carries a 25 % allowance for sampling noise (1 when no such selection
+// was seen).
+double cover_bound(const imm_server* S, const Query& q) {
+    const double first_phase = std::ceil(q.plan.lam1 / ((double)S->g->n / 2.0));
+    double c = 1.0;
+    for (const imm_server::Seen& o : S->cov_seen[q.model]) {
+        const size_t r = o.cum.size();
+        if (r == 0 || (double)o.sets > first_phase) continue;
+        const size_t k = (size_t)q.k;
+        const double at = k <= r ? o.cum[k - 1]
+                                 : o.cum[r - 1] + (double)(k - r) * (o.cum[r - 1] - (r >= 2 ? o.cum[r - 2] : 0.0));
+        c = std::min(c, 1.25 * at);
+    }
+    return std::max(c, 1e-12);
+}
+
+double step_bytes(const imm_server* S, const Query& q) {
+    // theta = lambda* / LB with LB = n c / (1 + eps') for the passing phase's coverage c
+    const double final_min = std::ceil(q.plan.lam2 * (1.0 + q.plan.ep) / ((double)S->g->n * cover_bound(S, q)));
+    return bytes_for(S, q, std::max((double)q.gen_upto, final_min),
+                     std::max((double)q.sel_count, final_min));
+}
+
+// After a failed estimation phase (coverage fraction c of its k seeds): the phase that
+// passes has x <= n c' / (1 + eps') with c' its own coverage fraction, about c (greedy on
+// the smaller sample tends to overstate it), so it reads about lambda' (1 + eps') / (n c)
+// sets.  Bytes of that phase (lambda* when the seeds covered nothing).
+double predicted_pass_bytes(const imm_server* S, const Query& q, int64_t cov, int64_t count) {
+    const double n = (double)S->g->n;
+    const ImmPlan& P = q.plan;
+    const double sets = cov > 0 ? P.lam1 * (1.0 + P.ep) / (n * ((double)cov / (double)count)) : P.lam2;
+    return bytes_for(S, q, sets, sets);
+}
+
+void finish(imm_server* S, Query& q, imm_status st, const std::string& err);
+
+bool pool_in_use(const imm_server* S, int m, const std::vector<Query>* also = nullptr) {
+    for (const Query& q : S->active)
+        if (q.model == m) return true;
+    if (also)
+        for (const Query& q : *also)
+            if (q.model == m) return true;
+    return false;
+}
+
+// Device bytes held by the pools of the other model while queries read them.
+double pinned_bytes(const imm_server* S, int m, const std::vector<Query>* also = nullptr) {
+    const int o = 1 - m;
+    return S->pools[o] && pool_in_use(S, o, also) ? (double)S->pools[o]->bytes() : 0.0;
+}
+
+// Drops the sets of a pool that no active query reads, to give its memory to queries that
+// need it (a pool's sets are a pure function of its seed: a later query that reads them
+// draws them again, identically).  Returns the device bytes given back.
+double reset_idle_pool(imm_server* S, int m, const std::vector<Query>* also = nullptr) {
+    imm_pool* p = S->pools[m];
+    if (!p || p->count == 0 || pool_in_use(S, m, also)) return 0.0;
+    imm_pool* fresh = nullptr;
+    if (imm_pool_create(S->g, (imm_model)m, S->seeds[m], &fresh) != IMM_OK) return 0.0;
+    const double freed = (double)p->bytes() - (double)fresh->bytes();
+    for (SelectWs& w : S->slots)
+        if (w.ix_pool == p) {
+            w.ix_pool = nullptr;
+            w.snap_valid = false;
+        }
+    imm_pool_destroy(p);
+    S->pools[m] = fresh;
+    S->pool_sets[m].store(0);
+    S->pool_resets += 1;
+    return freed;
+}
+
+void reject_budget(imm_server* S, Query& q, double need) {
+    char msg[200];
+    snprintf(msg, sizeof msg,
+             "query needs about %.3g bytes of device memory (its final selection reads at least "
+             "%.3g RR sets), more than the server budget of %lld",
+             need, std::ceil(q.plan.lam2 * (1.0 + q.plan.ep) / ((double)S->g->n * cover_bound(S, q))),
+             (long long)S->budget);
+    finish(S, q, IMM_ECAPACITY, msg);
 }
 
 // Sets generated first on an empty pool, to measure its mean set size before any query's
@@ -183,7 +288,12 @@ bool tick(imm_server* S) {
             Query& q = S->queue.front();
             const int64_t need = query_bytes(S, q, false);
             const int64_t used = S->device_bytes();
-            if (!S->active.empty() && used + need > S->budget) break;   // wait for memory
+            if (!S->active.empty() && used + need > S->budget) {
+                // the memory of a pool no active query reads goes to the waiting query;
+                // otherwise it waits for memory
+                if (reset_idle_pool(S, 1 - q.model) > 0.0 || reset_idle_pool(S, q.model) > 0.0) continue;
+                break;
+            }
             q.slot = S->free_slots.back();
             S->free_slots.pop_back();
             q.t_admit = now_s();
@@ -196,6 +306,9 @@ bool tick(imm_server* S) {
     S->ticks += 1;
     S->bytes_snapshot.store(S->device_bytes());
     std::vector<Query>& act = S->active;
+    const double t_tick = now_s();
+    double tr_gen[2] = {0.0, 0.0};
+    int64_t tr_sets = 0;
     // 1. next selection of every active query
     for (size_t i = 0; i < act.size();) {
         Query& q = act[i];
@@ -205,9 +318,97 @@ bool tick(imm_server* S) {
             act.erase(act.begin() + (long)i);
             continue;
         }
+        // once its pool's set size is measured, a query whose final selection cannot fit the
+        // budget leaves before any work on it (the same test as before a pool grows)
+        const imm_pool* p = S->pools[q.model];
+        if (p && p->count >= kPilotSets && !q.plan.reuses_last()) {
+            const double need = step_bytes(S, q) + pinned_bytes(S, q.model);
+            if (need > (double)S->budget) {
+                reject_budget(S, q, need);
+                act.erase(act.begin() + (long)i);
+                continue;
+            }
+        }
         ++i;
     }
     if (act.empty()) return true;
+    // 1b. the tick's added demand (pools grown to the largest step, every step's selection
+    //     workspace) must fit what the budget and the device have left: the most recently
+    //     admitted queries sit this tick out (their workspace memory given back) until it
+    //     does, the oldest one always runs.  Without this, queries admitted together could
+    //     each fit alone and run out of device memory together as their estimation phases
+    //     grow.
+    //     A query whose final selection repeats its last one (no selection, no memory)
+    //     is never held: its result sits in its workspace.
+    std::vector<Query> held;
+    struct Restore {             // held queries rejoin the active list however the tick ends
+        std::vector<Query>& act;
+        std::vector<Query>& held;
+        ~Restore() {             // newest was held first: rejoin oldest first
+            for (auto it = held.rbegin(); it != held.rend(); ++it) act.push_back(std::move(*it));
+        }
+    } restore{act, held};
+    {
+        // room: what the budget leaves and what the device has (free plus the allocator's
+        // cache, which is given back when an allocation fails), less a margin
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = 0;
+        }
+        const double margin = (double)((int64_t)2 << 30);
+        double room = std::min((double)S->budget - (double)S->device_bytes(),
+                               (double)free_b + (double)dev_cached_bytes() - margin);
+        const double n = (double)S->g->n;
+        auto ws_growth = [&](const Query& q) {
+            if (q.plan.reuses_last()) return 0.0;
+            const double need = n * 20.0 + (double)q.sel_count * (S->mean_members[q.model].load() * 4.0 + 4.0);
+            return std::max(0.0, need - (double)S->slots[q.slot].bytes());
+        };
+        // transient bytes of growing a pool to `target` sets: new offset / length arrays
+        // and a new id buffer (capacities double; old and new coexist during the copy),
+        // plus the heavy-kernel scratch of a pool that has none yet
+        auto pool_growth = [&](int m, int64_t target) {
+            const imm_pool* p = S->pools[m];
+            if (!p || target <= p->count) return 0.0;
+            double b = 0.0;
+            auto grown = [](int64_t cap, double need) {
+                double c = cap > 0 ? (double)cap : 1024.0;
+                while (c < need) c *= 2.0;
+                return c;
+            };
+            if (target > p->cap_sets) b += grown(p->cap_sets, (double)target) * 12.0;
+            const double ids = (double)p->sum.placed +
+                               (double)(target - p->count) * S->mean_members[m].load() * 1.3 + (1 << 24);
+            if (ids > (double)p->cap_ids) b += grown(p->cap_ids, ids) * 4.0;
+            b += (double)p->gen.heavy_bytes(S->g->n);
+            return b;
+        };
+        for (;;) {
+            double need = 0.0;
+            int64_t target[2] = {0, 0};
+            for (const Query& q : act) {
+                target[q.model] = std::max(target[q.model], q.gen_upto);
+                need += ws_growth(q);
+            }
+            need += pool_growth(0, target[0]) + pool_growth(1, target[1]);
+            if (need <= room) break;
+            // first the memory of pools no query of this tick reads
+            const double freed = reset_idle_pool(S, 0, &held) + reset_idle_pool(S, 1, &held);
+            if (freed > 0.0) {
+                room += freed;
+                continue;
+            }
+            size_t at = act.size();              // the newest query that may sit out
+            while (at > 1 && act[at - 1].plan.reuses_last()) --at;
+            if (at <= 1) break;                  // the oldest query always runs
+            Query& q = act[at - 1];
+            room += (double)S->slots[q.slot].bytes();
+            S->slots[q.slot].release();
+            held.push_back(std::move(q));
+            act.erase(act.begin() + (long)(at - 1));
+        }
+    }
     // 2. one generation per pool, to the largest demand.  An empty pool first gets a pilot
     //    of kPilotSets sets (the same sets any query reads first) so that the mean set size
     //    is measured; then queries whose step cannot fit the budget are rejected, and the
@@ -249,14 +450,9 @@ bool tick(imm_server* S) {
                 continue;
             }
             q.t_gen += t_pilot;
-            const double need = step_bytes(S, q);
+            const double need = step_bytes(S, q) + pinned_bytes(S, m, &held);
             if (need > (double)S->budget) {
-                char msg[160];
-                snprintf(msg, sizeof msg,
-                         "query needs about %.3g bytes of device memory for %lld RR sets, more than "
-                         "the server budget of %lld",
-                         need, (long long)q.gen_upto, (long long)S->budget);
-                finish(S, q, IMM_ECAPACITY, msg);
+                reject_budget(S, q, need);
                 act.erase(act.begin() + (long)i);
                 continue;
             }
@@ -267,6 +463,7 @@ bool tick(imm_server* S) {
         const double t0 = now_s();
         imm_status st = pool_generate(p, target, S->stream);
         const double dt = now_s() - t0;
+        tr_gen[m] += dt + t_pilot;
         if (st == IMM_OK && p->count > 0)
             S->mean_members[m].store((double)p->sum.placed / (double)p->count);
         S->pool_sets[m].store(p->count);
@@ -298,6 +495,7 @@ bool tick(imm_server* S) {
             continue;
         }
         si.need = q.plan.need_cov();
+        tr_sets += q.sel_count;
         ws.push_back(&S->slots[q.slot]);
         inst.push_back(si);
         ++i;
@@ -313,16 +511,60 @@ bool tick(imm_server* S) {
         return false;
     }
     // 4. advance every query
+    const size_t tr_ran = act.size();
     for (size_t i = 0; i < act.size();) {
         Query& q = act[i];
         q.t_sel += dt;
-        imm_status cs = q.plan.complete((int64_t)*S->slots[q.slot].host_cov);
+        const bool estimating = !q.plan.final_phase;
+        const int64_t cov = (int64_t)*S->slots[q.slot].host_cov;
+        if (!q.plan.reuses_last() && q.sel_count > 0) {
+            // gains of the rounds run (a stopped phase ends early)
+            imm_server::Seen o{{}, q.sel_count};
+            const unsigned long long* keys = S->slots[q.slot].host_keys;
+            double acc = 0.0;
+            for (int32_t j = 0; j < q.k && keys[j] != 0; ++j) {
+                acc += (double)((keys[j] >> 32) - 1);
+                o.cum.push_back(acc / (double)q.sel_count);
+            }
+            auto& seen = S->cov_seen[q.model];
+            if (seen.size() >= 32) seen.erase(seen.begin());
+            if (!o.cum.empty()) seen.push_back(std::move(o));
+        }
+        imm_status cs = q.plan.complete(cov);
         if (cs != IMM_OK || q.plan.done) {
             finish(S, q, cs, cs == IMM_OK ? "" : imm_last_error());
             act.erase(act.begin() + (long)i);
             continue;
         }
+        if (estimating && !q.plan.final_phase) {
+            // the phase failed: a query whose passing phase cannot fit the budget leaves now
+            // rather than after the phases in between
+            const double need = predicted_pass_bytes(S, q, cov, q.sel_count) + pinned_bytes(S, q.model, &held);
+            if (need > (double)S->budget) {
+                char msg[200];
+                snprintf(msg, sizeof msg,
+                         "query's estimation would need about %.3g bytes of device memory (its "
+                         "seeds covered %lld of %lld RR sets), more than the server budget of %lld",
+                         need, (long long)cov, (long long)q.sel_count, (long long)S->budget);
+                finish(S, q, IMM_ECAPACITY, msg);
+                act.erase(act.begin() + (long)i);
+                continue;
+            }
+        }
         ++i;
+    }
+    if (S->trace) {
+        fprintf(stderr,
+                "[imm serve] tick %lld: %zu ran, %zu held; generation IC %.3f s (%lld sets), LT "
+                "%.3f s (%lld sets); %zu selections over %lld sets %.3f s; tick %.3f s; %.1f GB\n",
+                (long long)S->ticks, tr_ran, held.size(), tr_gen[0],
+                S->pools[0] ? (long long)S->pools[0]->count : 0ll, tr_gen[1],
+                S->pools[1] ? (long long)S->pools[1]->count : 0ll, inst.size(), (long long)tr_sets, dt,
+                now_s() - t_tick, (double)S->device_bytes() * 1e-9);
+    }
+    if (S->frugal) {
+        reset_idle_pool(S, IMM_IC, &held);
+        reset_idle_pool(S, IMM_LT, &held);
     }
     return true;
 }
@@ -376,6 +618,10 @@ extern "C" imm_status imm_server_create(const imm_graph* g, uint64_t seed_ic, ui
     S->g = g;
     S->budget = hbm_budget_bytes;
     S->max_active = max_active;
+    S->seeds[IMM_IC] = seed_ic;
+    S->seeds[IMM_LT] = seed_lt;
+    if (const char* e = getenv("IMM_SERVE_TRACE")) S->trace = atoi(e) != 0;
+    if (const char* e = getenv("IMM_SERVE_FRUGAL")) S->frugal = atoi(e) != 0;
     imm_status st = IMM_OK;
     if (g->has_ic) st = imm_pool_create(g, IMM_IC, seed_ic, &S->pools[IMM_IC]);
     if (st == IMM_OK && g->has_lt) st = imm_pool_create(g, IMM_LT, seed_lt, &S->pools[IMM_LT]);
@@ -398,7 +644,8 @@ extern "C" imm_status imm_server_submit(imm_server* S, int32_t k, double eps, do
                                         imm_model model, int32_t fresh_final, uint64_t* ticket) {
     if (!S || !ticket) return fail(IMM_EINVAL, "NULL argument");
     if (model != IMM_IC && model != IMM_LT) return fail(IMM_EINVAL, "unknown model %d", (int)model);
-    if (!S->pools[model]) return fail(IMM_EINVAL, "graph has no encoding for model %d", (int)model);
+    if (!(model == IMM_IC ? S->g->has_ic : S->g->has_lt))
+        return fail(IMM_EINVAL, "graph has no encoding for model %d", (int)model);
     Query q;
     IMM_TRY(q.plan.init(S->g->n, k, eps, ell, fresh_final));
     q.k = k;
@@ -486,6 +733,7 @@ extern "C" imm_status imm_server_stats_get(imm_server* S, imm_server_stats* out)
     out->pool_sets_ic = S->pool_sets[IMM_IC].load();
     out->pool_sets_lt = S->pool_sets[IMM_LT].load();
     out->device_bytes = S->bytes_snapshot.load();
+    out->pool_resets = S->pool_resets.load();
     return IMM_OK;
 }
 

@@ -1,9 +1,12 @@
 // Autotuning of the RR-generation launch configuration for one graph and model.
 //
-// Two knobs shape the generation launches: the light-wave budget (4-edge groups a set may
-// examine before it is handed to the heavy kernel) and the threads per heavy set.  The
-// best values depend on the graph's degree distribution and probabilities (how many sets
-// overflow, how large they get).  imm_autotune times the generation of the same pilot sets
+// Four knobs shape the generation launches: the light-wave budget (4-edge groups a set may
+// examine before it is handed to the heavy kernel), the threads per heavy set, the on-chip
+// list capacity of a light set or LT walk (frontier capacity: beyond it the set moves to
+// the heavy kernel / the walk to its extension list), and the RR indices a wave takes per
+// fetch from the launch's work counter (queue depth).  The best values depend on the
+// graph's degree distribution and probabilities (how many sets overflow, how large they
+// get).  imm_autotune times the generation of the same pilot sets
 // under each candidate and keeps the fastest for later pools of that graph and model.  RR
 // sets never depend on the configuration (each draw is keyed by (seed, r, edge)), so
 // tuning changes speed only.
@@ -43,33 +46,68 @@ extern "C" imm_status imm_autotune(imm_graph* g, imm_model model, uint64_t seed,
     if ((model == IMM_IC && !g->has_ic) || (model == IMM_LT && !g->has_lt))
         return fail(IMM_EINVAL, "graph has no encoding for model %d", (int)model);
     if (pilot_sets < 1 || pilot_sets > kMaxSets) return fail(IMM_EINVAL, "pilot_sets out of range");
-    std::vector<GenTuning> cand;
-    for (int64_t b : {1024, 2048, 4096, 8192, 16384})
-        for (int hb : {128, 256}) cand.push_back(GenTuning{b, hb});
-    if (model == IMM_LT) {   // LT has no budget or heavy block size: one measurement
-        cand.assign(1, GenTuning{4096, 256});
-    }
+    // The library defaults, then one knob group at a time (coordinate descent): IC light
+    // budget x heavy block size, then the light list capacity, then the fetch depth; LT
+    // the walk list capacity, then the fetch depth.
+    const GenTuning dflt{4096, 256, 1024, kLtLdsCap, kGenFetch};
+    GenTuning best = dflt;
     double warm = 0.0;
-    IMM_TRY(time_generation(g, model, seed, pilot_sets, cand[0], &warm));   // first-use costs
-    double best = 0.0, def = 0.0;
-    size_t best_i = 0;
-    for (size_t i = 0; i < cand.size(); ++i) {
+    IMM_TRY(time_generation(g, model, seed, pilot_sets, dflt, &warm));   // first-use costs
+    double t_best = 0.0, t_def = 0.0;
+    IMM_TRY(time_generation(g, model, seed, pilot_sets, dflt, &t_def));
+    t_best = t_def;
+    int32_t timed = 1;
+    auto consider = [&](const GenTuning& c) -> imm_status {
         double t = 0.0;
-        IMM_TRY(time_generation(g, model, seed, pilot_sets, cand[i], &t));
-        if (cand[i].budget == 4096 && cand[i].heavy_block == 256) def = t;
-        if (i == 0 || t < best) {
-            best = t;
-            best_i = i;
+        IMM_TRY(time_generation(g, model, seed, pilot_sets, c, &t));
+        ++timed;
+        if (t < t_best) {
+            t_best = t;
+            best = c;
+        }
+        return IMM_OK;
+    };
+    if (model == IMM_IC) {
+        const GenTuning base = best;
+        for (int64_t b : {1024, 2048, 4096, 8192, 16384})
+            for (int hb : {128, 256}) {
+                GenTuning c = base;
+                c.budget = b;
+                c.heavy_block = hb;
+                if (b == dflt.budget && hb == dflt.heavy_block) continue;
+                IMM_TRY(consider(c));
+            }
+        const GenTuning b2 = best;
+        for (int cap : {256, 512}) {
+            GenTuning c = b2;
+            c.light_cap = cap;
+            IMM_TRY(consider(c));
+        }
+    } else {
+        const GenTuning b2 = best;
+        for (int cap : {64, 128}) {
+            GenTuning c = b2;
+            c.lt_cap = cap;
+            IMM_TRY(consider(c));
         }
     }
-    g->tuned[model] = cand[best_i];
+    const GenTuning b3 = best;
+    for (int f : {4, 16, 32}) {
+        GenTuning c = b3;
+        c.fetch = f;
+        IMM_TRY(consider(c));
+    }
+    g->tuned[model] = best;
     if (out) {
         memset(out, 0, sizeof *out);
-        out->light_budget = cand[best_i].budget;
-        out->heavy_block = cand[best_i].heavy_block;
-        out->candidates = (int32_t)cand.size();
-        out->best_sets_per_s = best > 0 ? (double)pilot_sets / best : 0.0;
-        out->default_sets_per_s = def > 0 ? (double)pilot_sets / def : 0.0;
+        out->light_budget = best.budget;
+        out->heavy_block = best.heavy_block;
+        out->candidates = timed;
+        out->best_sets_per_s = t_best > 0 ? (double)pilot_sets / t_best : 0.0;
+        out->default_sets_per_s = t_def > 0 ? (double)pilot_sets / t_def : 0.0;
+        out->light_cap = best.light_cap;
+        out->lt_cap = best.lt_cap;
+        out->fetch = best.fetch;
     }
     return IMM_OK;
 }

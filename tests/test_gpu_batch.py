@@ -128,3 +128,22 @@ def test_batch_validates_before_work(imm_gpu, mix):
     bad[0]["model"] = imm.IMM_LT
     with pytest.raises(imm.ImmError):
         imm.imm_batch_solve(bad)
+
+
+def test_batch_graph_ticks_equal_direct_ticks(imm_gpu, mix, monkeypatch):
+    """With IMM_BATCH_GRAPH=1 the selection half of every tick runs as one captured graph;
+    the results equal those of the same batch without capture (the default), and the
+    captured path was the one taken."""
+    imm = imm_gpu
+    monkeypatch.setenv("IMM_BATCH_GRAPH", "1")
+    st_g = {}
+    res_g = imm.imm_batch_solve(mix, stats=st_g)
+    assert st_g["graph_ticks"] == st_g["ticks"] > 0
+    monkeypatch.setenv("IMM_BATCH_GRAPH", "0")
+    st_d = {}
+    res_d = imm.imm_batch_solve(mix, stats=st_d)
+    assert st_d["graph_ticks"] == 0
+    for (s1, i1), (s2, i2) in zip(res_g, res_d):
+        assert np.array_equal(s1, s2)
+        assert all(i1[k] == i2[k] for k in KEYS)
+

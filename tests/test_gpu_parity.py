@@ -83,6 +83,27 @@ def test_rr_sets_ic_per_edge_thresholds(imm_gpu):
     _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 99, 20_000, ic_p=p)
 
 
+@pytest.mark.parametrize("block,budget", [("256", None), ("1024", None), ("256", "16")])
+def test_rr_sets_ic_bounded_heavy_lists(imm_gpu, monkeypatch, block, budget):
+    """Heavy member lists bounded to 1024 entries (as on huge graphs, where full lists would
+    leave too few slots): a set that outgrows its list is dropped and drawn again from its
+    root in a full list.  Sets, histogram and in-edges examined must equal the oracle's
+    (p = 0.12 on a random graph: ~600 of 2000 sets exceed 1024 members, a few dozen fall
+    between 64 and 1024), and a solve must report sets drawn again."""
+    monkeypatch.setenv("IMM_HEAVY_LIST", "1024")
+    monkeypatch.setenv("IMM_HEAVY_BLOCK", block)
+    if budget:
+        monkeypatch.setenv("IMM_LIGHT_BUDGET", budget)
+    g = graphs.erdos_renyi(5000, 50_000, seed=51)
+    p = np.full(g.m, 0.12, dtype=np.float32)
+    _, ref = _compare_pool(imm_gpu, g, imm_gpu.IMM_IC, 0x5EED0601, 2000, ic_p=p, chunks=[300, 2000])
+    sizes = np.diff(ref.export()[0])
+    assert (sizes > 1024).sum() > 500 and ((sizes > 64) & (sizes <= 1024)).sum() > 10
+    _, info, _ = _solve_both(imm_gpu, g, imm_gpu.IMM_IC, 5, 0.5, 1.0, 0x5EED0602,
+                             ic_p=np.full(g.m, 0.15, dtype=np.float32))
+    assert info["heavy_redrawn"] > 0
+
+
 @pytest.mark.parametrize("budget", ["2", "16"])
 def test_rr_sets_ic_handoff(imm_gpu, monkeypatch, budget):
     """A light budget of a few 4-edge groups: almost every set with more than one level is

@@ -125,3 +125,32 @@ def test_server_rejects_query_whose_pool_would_outgrow_budget(imm_gpu):
         s_alone, i_alone = imm.imm_solve(gg.handle, k, 0.5, 1.0, imm.IMM_IC, SEED_IC)
         assert np.array_equal(seeds, s_alone)
         assert info["theta"] == i_alone["theta"] and info["covered"] == i_alone["covered"]
+
+
+def test_served_results_equal_solo_after_pool_resets(imm_gpu, served_graph, monkeypatch):
+    """A pool that no active query reads may be emptied to give its memory to others; its
+    sets are drawn again, identically, when a later query needs them.  With
+    IMM_SERVE_FRUGAL=1 the server empties every such pool after each tick, so queries of
+    one model that follow queries of the other redraw their pool: every answer must still
+    equal the solo solve."""
+    g, p, gg = served_graph
+    imm = imm_gpu
+    monkeypatch.setenv("IMM_SERVE_FRUGAL", "1")
+    qs = [dict(k=8, eps=0.3, model=0), dict(k=5, eps=0.5, model=1), dict(k=20, eps=0.2, model=0),
+          dict(k=12, eps=0.3, model=1), dict(k=3, eps=0.5, model=0)]
+    srv = imm.imm_server_create(gg.handle, SEED_IC, SEED_LT, 8 << 30, 1)
+    try:
+        results = []
+        for q in qs:                        # one at a time: the other model's pool is idle
+            t = imm.imm_server_submit(srv, q["k"], q["eps"], 1.0, q["model"])
+            results.append(imm.imm_server_wait(srv, t, q["k"], timeout_s=60))
+        stats = imm.imm_server_stats_get(srv)
+    finally:
+        imm.imm_server_destroy(srv)
+    assert stats["completed"] == len(qs) and stats["pool_resets"] >= 3
+    for q, (seeds, info) in zip(qs, results):
+        s_alone, i_alone = _alone(imm, gg, q)
+        assert np.array_equal(seeds, s_alone), q
+        for key in ("theta", "covered", "phases", "num_rr"):
+            assert info[key] == i_alone[key], (q, key)
+        assert info["lb"] == i_alone["lb"]

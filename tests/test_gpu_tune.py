@@ -1,7 +1,7 @@
 """Autotuning: the chosen launch configuration changes speed, never results.
 
-imm_autotune times pilot generation under each candidate (light-wave budget x heavy block
-size) and stores the fastest on the graph.  Every RR set is keyed by (seed, set, edge), so
+imm_autotune times pilot generation under candidate launch configurations (light-wave
+budget x heavy block size, list capacity, fetch depth) and stores the fastest on the graph.  Every RR set is keyed by (seed, set, edge), so
 pools and solves after tuning must be bit-identical to those before it.
 """
 import numpy as np
@@ -37,15 +37,19 @@ def test_tuned_results_equal_default(imm_gpu, kind):
     before_sets = _sets(imm, gg, model, seed, 3000)
     before = imm.imm_solve(gg.handle, k, eps, 1.0, model, seed)
     info = imm.imm_autotune(gg.handle, model, seed, 2000)
+    assert info["fetch"] in (4, 8, 16, 32)
+    assert info["default_sets_per_s"] > 0
+    # the chosen configuration was the fastest measured, the default among them
+    assert info["best_sets_per_s"] >= info["default_sets_per_s"]
     if model == imm.IMM_IC:
-        assert info["candidates"] == 10
+        # defaults, 9 other budget x block pairs, 2 list capacities, 3 fetch depths
+        assert info["candidates"] == 15
         assert info["light_budget"] in (1024, 2048, 4096, 8192, 16384)
         assert info["heavy_block"] in (128, 256)
-        assert info["default_sets_per_s"] > 0
-        # the chosen configuration was the fastest measured, the default among them
-        assert info["best_sets_per_s"] >= info["default_sets_per_s"]
+        assert info["light_cap"] in (256, 512, 1024)
     else:
-        assert info["candidates"] == 1
+        assert info["candidates"] == 6          # defaults, 2 walk list capacities, 3 depths
+        assert info["lt_cap"] in (64, 128, 256)
     after_sets = _sets(imm, gg, model, seed, 3000)
     for a, b in zip(before_sets, after_sets):
         assert np.array_equal(a, b)
