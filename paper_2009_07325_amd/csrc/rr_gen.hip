@@ -981,17 +981,28 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
 // unused load), and the revisit scans, placements of finished walks and starts of new
 // walks of the wave all run while those loads travel.  A new walk's root record is
 // likewise loaded one iteration before its first draw.
+//
+// The scan runs only when the picked vertex may be on the walk: each walk keeps a
+// 4096-bit filter in LDS (one bit per member, at a multiplicative hash of its id), and a
+// clear bit proves the vertex new.  A walk of L members scans with probability at most
+// L / 4096 per step, so long walks no longer pay a scan of their whole list (the
+// extension part in HBM) at every step.
 // ------------------------------------------------------------------------------------
 constexpr int kLtGroup = 16;
 constexpr int kLtWalks = kWave / kLtGroup;
+constexpr int kLtFiltWords = 128;
+
+__device__ __forceinline__ uint32_t lt_filt_bit(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> 20; }
 
 __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
     __shared__ int32_t lists[kWavesPerBlock][kLtWalks][kLtLdsCap];
+    __shared__ uint32_t filts[kWavesPerBlock][kLtWalks][kLtFiltWords];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     const int grp = lane / kLtGroup, gl = lane % kLtGroup;
     const uint64_t gmask = 0xFFFFull << (grp * kLtGroup);
     int32_t* list = lists[wib][grp];
+    uint32_t* filt = filts[wib][grp];
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
     const int32_t lcap = G.lt_lds_cap, ecap = G.lt_ext_cap;
     IMM_GLOBAL int32_t* ext_wave = global(G.lt_ext) + slot * kLtWalks * (int64_t)ecap;
@@ -1049,10 +1060,13 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
                     ugi = 2 * (int64_t)ustart + (int64_t)(((uint64_t)ux * (2ull * udeg)) >> 32);
                     urec = load_ltrec(T.grec + ugi);
                 }
+                const uint32_t hb = lt_filt_bit(u);
                 bool hit = false;
-                const int32_t in_lds = min(size, lcap);
-                for (int32_t i = gl; i < in_lds; i += kLtGroup) hit |= list[i] == u;
-                for (int32_t i = gl; i < size - lcap; i += kLtGroup) hit |= ext[i] == u;
+                if ((filt[hb >> 5] >> (hb & 31)) & 1u) {    // u may be on the walk
+                    const int32_t in_lds = min(size, lcap);
+                    for (int32_t i = gl; i < in_lds; i += kLtGroup) hit |= list[i] == u;
+                    for (int32_t i = gl; i < size - lcap; i += kLtGroup) hit |= ext[i] == u;
+                }
                 if ((ballot(hit) & gmask) != 0) {
                     done = true;                        // u is already on the walk
                 } else if (size >= lcap + ecap) {
@@ -1062,6 +1076,7 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
                     if (gl == 0) {
                         if (size < lcap) list[size] = u;
                         else ext[size - lcap] = u;
+                        filt[hb >> 5] |= 1u << (hb & 31);
                     }
                     ++size;
                     // the group's later scans read the extension entry written above
@@ -1119,7 +1134,12 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
                 t = I.round;
                 v = (int32_t)root_of(r, (uint32_t)I.n, k0, k1);
                 vr = load_vrec(global(I.vrec) + v);
-                if (gl == 0) list[0] = v;
+                for (int i = gl; i < kLtFiltWords; i += kLtGroup) filt[i] = 0u;
+                if (gl == 0) {
+                    list[0] = v;
+                    const uint32_t hb = lt_filt_bit(v);
+                    filt[hb >> 5] |= 1u << (hb & 31);
+                }
                 size = 1;
                 examined = 0;
                 phase = 0;
