@@ -282,7 +282,7 @@ static imm_status graph_create_impl(imm_graph* g, const int64_t* in_off, const i
         G_HIP(hipMemset(g->cum, 0, sizeof(uint32_t) * (size_t)m_pad));
         G_HIP(launch_encode_lt(n, d_off, d_w, g->cum, s));
         G_TRY(dalloc(&g->lrec, m));
-        G_TRY(dalloc(&g->grec, 2 * m));
+        G_TRY(dalloc(&g->grec, 4 * m));
         G_TRY(dalloc(&g->gidx, 2 * m));
         G_HIP(launch_build_lt_tables(n, m, g->cum, g->src, g->vrec, g->lrec, g->grec, g->gidx, s));
         g->has_lt = true;

@@ -175,7 +175,10 @@ __global__ void k_build_lrec(int64_t m, const uint32_t* __restrict__ cum, const 
 }
 
 // One wave per vertex, lanes over its in-edges.  The guide of bucket b is the first edge j
-// with cum_j > L_b (a saturated threshold counts as 2^32), i.e. the edge with
+// with cum_j > L_b (a saturated threshold counts as 2^32); bucket b's 32-byte slot holds
+// edge j's record and then edge j+1's (j's again for the last edge), since a draw that
+// passes cum_j inside the bucket most often picks j+1, which then costs a load from the
+// same cache line rather than a second dependent one.  Edge j is the edge with
 // cum_{j-1} <= L_b < cum_j, so edge j is the guide of exactly the buckets whose lower end
 // lies in [cum_{j-1}, cum_j): b in [first(cum_{j-1}), first(cum_j)), where first(c), the
 // smallest b with L_b >= c, is 0 for c = 0 and floor((c - 1) 2d / 2^32) + 1 otherwise
@@ -206,8 +209,10 @@ __global__ void k_build_guide(int32_t n, const VRec* __restrict__ vrec, const ui
             const uint64_t b_hi = min(first_bucket(hi_c, nb), nb);
             if (b_lo >= b_hi) continue;
             const LtRec rec = lrec[s + j];
+            const LtRec nxt = j + 1 < d ? lrec[s + j + 1] : rec;
             for (uint64_t b = b_lo; b < b_hi; ++b) {
-                grec[2 * s + (int64_t)b] = rec;
+                grec[2 * (2 * s + (int64_t)b)] = rec;
+                grec[2 * (2 * s + (int64_t)b) + 1] = nxt;
                 gidx[2 * s + (int64_t)b] = j;
             }
         }

@@ -193,8 +193,8 @@ struct imm_graph {
     int32_t* src = nullptr;
     uint32_t* thr = nullptr;     // IC thresholds (padded to a multiple of 4 edges)
     uint32_t* cum = nullptr;     // LT cumulative thresholds
-    imm::LtRec* lrec = nullptr;  // LT walk tables: edge records (m), guide records (2m)
-    imm::LtRec* grec = nullptr;
+    imm::LtRec* lrec = nullptr;  // LT walk tables: edge records (m), guide records (2m
+    imm::LtRec* grec = nullptr;  // pairs: the guide edge's record, then its successor's)
     uint32_t* gidx = nullptr;    // ... and guide positions (2m)
     bool has_ic = false, has_lt = false;
     bool ic_uniform = false;     // every vertex has one common IC threshold

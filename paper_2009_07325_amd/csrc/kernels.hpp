@@ -67,7 +67,7 @@ struct GenInst {
     const uint32_t* thr;     // IC per-edge thresholds (padded to a multiple of 4 edges)
     const uint32_t* cum;     // LT cumulative thresholds
     const LtRec* lrec;       // LT walk tables (edge records, guide records and positions)
-    const LtRec* grec;
+    const LtRec* grec;       // pairs: guide record, successor's record (4m)
     const uint32_t* gidx;
     int32_t n;
     uint32_t k0, k1;         // Philox key (pool seed)

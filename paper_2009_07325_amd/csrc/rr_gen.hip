@@ -895,13 +895,16 @@ __device__ __forceinline__ LtTables lt_tables(const GenInst& I) {
 // The in-edge of a vertex with in-edges [start, start + deg), deg > 0, that draw x picks.
 __device__ __forceinline__ LtRec lt_step(const LtTables& T, uint32_t start, uint32_t deg, uint32_t x) {
     const int64_t gi = 2 * (int64_t)start + (int64_t)(((uint64_t)x * (2ull * deg)) >> 32);
-    LtRec rec = load_ltrec(T.grec + gi);
+    LtRec rec = load_ltrec(T.grec + 2 * gi);
     if (!lt_ok(rec.cum, x)) {
-        uint32_t pos = T.gidx[gi];
-        do {
-            ++pos;
-            rec = load_ltrec(T.lrec + start + pos);
-        } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
+        rec = load_ltrec(T.grec + 2 * gi + 1);     // the successor (same cache line)
+        if (!lt_ok(rec.cum, x)) {
+            uint32_t pos = T.gidx[gi] + 1;
+            do {
+                ++pos;
+                rec = load_ltrec(T.lrec + start + pos);
+            } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
+        }
     }
     return rec;
 }
@@ -1036,18 +1039,22 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
                     examined += deg;
                     x = philox10(Ctr4{r, (uint32_t)v, t, kDomainLT}, k0, k1).x;
                     gi = 2 * (int64_t)start + (int64_t)(((uint64_t)x * (2ull * deg)) >> 32);
-                    rec = load_ltrec(T.grec + gi);
+                    rec = load_ltrec(T.grec + 2 * gi);
                     phase = 1;
                 }
             } else {
                 if (!lt_ok(rec.cum, x)) {
                     // a threshold inside the draw's bucket: the pick is one of the next
-                    // edges (the list's last edge is saturated, so the scan ends within it)
-                    uint32_t pos = T.gidx[gi];
-                    do {
-                        ++pos;
-                        rec = load_ltrec(T.lrec + start + pos);
-                    } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
+                    // edges, most often the successor, whose record shares the guide's
+                    // cache line (the list's last edge is saturated, so the scan ends)
+                    rec = load_ltrec(T.grec + 2 * gi + 1);
+                    if (!lt_ok(rec.cum, x)) {
+                        uint32_t pos = T.gidx[gi] + 1;
+                        do {
+                            ++pos;
+                            rec = load_ltrec(T.lrec + start + pos);
+                        } while (!lt_ok(rec.cum, x) && pos + 1 < deg);
+                    }
                 }
                 const int32_t u = rec.src;
                 const uint32_t ustart = rec.start, udeg = rec.deg;
@@ -1058,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
                 if (udeg > 0) {
                     ux = philox10(Ctr4{r, (uint32_t)u, t, kDomainLT}, k0, k1).x;
                     ugi = 2 * (int64_t)ustart + (int64_t)(((uint64_t)ux * (2ull * udeg)) >> 32);
-                    urec = load_ltrec(T.grec + ugi);
+                    urec = load_ltrec(T.grec + 2 * ugi);
                 }
                 const uint32_t hb = lt_filt_bit(u);
                 bool hit = false;
