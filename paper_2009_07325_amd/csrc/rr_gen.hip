@@ -994,8 +994,12 @@ __global__ __launch_bounds__(kBlock) void k_rr_lt_hbm(GenLaunch G) {
 constexpr int kLtGroup = 16;
 constexpr int kLtWalks = kWave / kLtGroup;
 constexpr int kLtFiltWords = 128;
+constexpr int kLtFiltLog2 = 12;              // filter bits: 2^12 = kLtFiltWords x 32
+static_assert((1 << kLtFiltLog2) == kLtFiltWords * 32, "filter hash width must match its words");
 
-__device__ __forceinline__ uint32_t lt_filt_bit(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> 20; }
+__device__ __forceinline__ uint32_t lt_filt_bit(int32_t u) {
+    return ((uint32_t)u * 0x9E3779B1u) >> (32 - kLtFiltLog2);
+}
 
 __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
     __shared__ int32_t lists[kWavesPerBlock][kLtWalks][kLtLdsCap];
@@ -1003,7 +1007,7 @@ __global__ __launch_bounds__(kBlock) void k_lt_groups(GenLaunch G) {
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     const int grp = lane / kLtGroup, gl = lane % kLtGroup;
-    const uint64_t gmask = 0xFFFFull << (grp * kLtGroup);
+    const uint64_t gmask = ((1ull << kLtGroup) - 1) << (grp * kLtGroup);
     int32_t* list = lists[wib][grp];
     uint32_t* filt = filts[wib][grp];
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wib;
