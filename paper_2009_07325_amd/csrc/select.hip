@@ -812,8 +812,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 }
             }
         }
+        if (solo && tid == 0) {                         // one instance: no scan needed
+            S.ent_pre[0] = 0;
+            S.ent_pre[1] = cnt;
+        }
         if (!__syncthreads_or(live)) return;            // every instance finished or stopped
-        block_excl_scan_i64(cnt, S.ent_pre, S.wsum);
+        if (!solo) block_excl_scan_i64(cnt, S.ent_pre, S.wsum);
         const int64_t nent = S.ent_pre[ninst];
         // Block b takes entries [nent b / G, nent (b+1) / G) in batches of one per thread:
         // each thread tests and marks its entry's set, and the batch's newly covered sets
