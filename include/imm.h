@@ -145,8 +145,10 @@ imm_status imm_pool_size(const imm_pool* p, int64_t* num_sets, int64_t* num_ids,
  * Errors: IMM_ECAPACITY if upto >= 2^32; IMM_ENOMEM. */
 imm_status imm_generate_rr(imm_pool* p, int64_t upto, void* stream);
 
-/* Canonical export of sets [first, first+count): off_out int64[count+1] (off_out[0] = 0)
- * and ids_out int32[ids_cap] with each set's members sorted ascending.  If ids_cap is too
+/* Canonical export of sets [first, first+count) (each the random RR set of gIM Sec. II-C:
+ * the vertices that reach the set's root in its live-edge instance): off_out
+ * int64[count+1] (off_out[0] = 0) and ids_out int32[ids_cap] with each set's members sorted
+ * ascending.  If ids_cap is too
  * small (or ids_out is NULL) only off_out and *ids_needed are written and IMM_ECAPACITY is
  * returned (ids_out == NULL returns IMM_OK). */
 imm_status imm_rr_export(const imm_pool* p, int64_t first, int64_t count, int64_t* off_out,
