@@ -490,7 +490,8 @@ extern "C" imm_status imm_rr_histogram(const imm_pool* pc, int64_t first, int64_
 // selection
 // ------------------------------------------------------------------------------------
 int64_t SelectWs::bytes() const {
-    int64_t b = (hot_bits ? (n + 31) / 32 * 4 + kSelectHotBuckets * 4 + 8 : 0) + hot_cap * 4;
+    int64_t b = (hot_bits ? (n + 31) / 32 * 4 + kSelectHotBuckets * 4 + 8 + n * 4 : 0) + hot_cap * 4 +
+                part_cap * 4;
     if (h) b += n * (4 + 4 + 8 + 4) + 8;
     for (const IndexSeg& x : seg) b += x.off ? (n + 1) * 8 + x.cap * 4 : 0;
     if (snap) b += n * 4;
@@ -524,7 +525,9 @@ void SelectWs::release() {
     dfree(cnt_hist);
     dfree(hot_n);
     dfree(hot_ids);
-    cap_cov = cap_k = hot_cap = 0;
+    dfree(hpos);
+    dfree(hot_part);
+    cap_cov = cap_k = hot_cap = part_cap = 0;
 }
 
 void SelectLaunch::release() {
@@ -593,6 +596,13 @@ static imm_status index_segment(imm_pool* p, SelectWs* w, const uint32_t* cnt, i
     return IMM_OK;
 }
 
+// Smallest gain of a dense selection round (IMM_SELECT_DENSE overrides, read at each
+// selection; 0 turns them off).
+int32_t imm::select_dense_gain() {
+    const char* e = getenv("IMM_SELECT_DENSE");
+    return e ? (int32_t)std::min(std::max(0ll, atoll(e)), 0x7FFFFFFFll) : (int32_t)2048;
+}
+
 int32_t imm::select_hot_max(int64_t n) {
     int64_t t = 16384;
     bool forced = false;
@@ -617,10 +627,18 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
             IMM_TRY(dalloc(&w->cnt_hist, kSelectHotBuckets));
             IMM_TRY(dalloc(&w->hot_n, 2));
         }
+        if (!w->hpos) IMM_TRY(dalloc(&w->hpos, n));
         if (hot_max > w->hot_cap) {
             dfree(w->hot_ids);
             IMM_TRY(dalloc(&w->hot_ids, hot_max));
             w->hot_cap = hot_max;
+        }
+        const int64_t part = (int64_t)select_coop_grid() * hot_max;
+        if (select_dense_gain() > 0 && hot_max <= kSelectDenseHot && part > w->part_cap &&
+            !no_alloc_active()) {
+            dfree(w->hot_part);
+            IMM_TRY(dalloc(&w->hot_part, part));
+            w->part_cap = part;
         }
     }
     const uint32_t* hsrc = nullptr;
@@ -661,7 +679,7 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
         HIP_TRY(launch_fill_u32(w->cnt_hist, kSelectHotBuckets, 0u, s));
         HIP_TRY(launch_fill_u32(w->hot_n, 2, 0u, s));
         HIP_TRY(launch_hot_prepare(hsrc, w->h, n, hot_max, w->cnt_hist, w->hot_bits, w->hot_ids,
-                                   w->hot_n, s));
+                                   w->hot_n, w->hpos, s));
     }
     HIP_TRY(launch_fill_u64(w->keys, k, 0ull, s));
     HIP_TRY(launch_fill_u64(w->n_covered, 1, 0ull, s));
@@ -695,6 +713,12 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
     si.hot_bits = w->hot_bits;
     si.hot_n = w->hot_n;
     si.hot_ids = w->hot_ids;
+    si.hpos = w->hpos;
+    if (hot_max > 0 && hot_max <= kSelectDenseHot &&
+        w->part_cap >= (int64_t)select_coop_grid() * hot_max) {
+        si.hot_part = w->hot_part;
+        si.dense_gain = select_dense_gain();
+    }
     *out = si;
     return IMM_OK;
 }

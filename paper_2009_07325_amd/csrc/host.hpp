@@ -249,6 +249,9 @@ struct SelectWs {
     uint32_t* hot_n = nullptr;
     int32_t* hot_ids = nullptr;               // hot_cap
     int64_t hot_cap = 0;
+    int32_t* hpos = nullptr;                  // n: position in hot_ids, -1 for a cold vertex
+    int32_t* hot_part = nullptr;              // part_cap: per-block decrement rows of dense rounds
+    int64_t part_cap = 0;
 
     int64_t bytes() const;
     void release();
@@ -393,6 +396,7 @@ imm_status select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t count
 // (IMM_SELECT_HOT overrides; 0 turns it off), used only when n exceeds twice that (or the
 // override), and at most kSelectHotPerBlock per block of the launch.
 int32_t select_hot_max(int64_t n);
+int32_t select_dense_gain();
 // Runs all rounds of every prepared instance in one cooperative launch, then copies each
 // instance's seeds and covered count to its workspace's pinned buffers (synchronises s).
 imm_status select_run(SelectLaunch* L, SelectWs* const* ws, const SelInst* inst, int32_t ninst,

@@ -170,10 +170,11 @@ hipError_t launch_sub_u32(const uint32_t* a, const uint32_t* b, uint32_t* out, i
 hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStream_t s);
 // Hot set of a single-instance selection: h = hist (as launch_copy_hist), the histogram of
 // the counts into cnt_hist (kSelectHotBuckets, zeroed), then the threshold and the hot list
-// into hot_bits (n bits, zeroed), hot_ids (hot_max) and hot_n (2 words, zeroed).
+// into hot_bits (n bits, zeroed), hot_ids (hot_max) and hot_n (2 words, zeroed), and every
+// vertex's position in hot_ids (-1: cold) into hpos (n).
 hipError_t launch_hot_prepare(const uint32_t* hist, int32_t* h, int64_t n, int32_t hot_max,
                               uint32_t* cnt_hist, uint32_t* hot_bits, int32_t* hot_ids,
-                              uint32_t* hot_n, hipStream_t s);
+                              uint32_t* hot_n, int32_t* hpos, hipStream_t s);
 // All k rounds of greedy selection for one or more instances in one cooperative launch:
 // per round a segmented argmax over every instance's counters, a grid barrier, the cover
 // step of every instance, a grid barrier.
@@ -225,9 +226,20 @@ struct SelInst {
     const uint32_t* hot_bits;
     const uint32_t* hot_n;
     const int32_t* hot_ids;
+    // Dense rounds (hot set of at most kSelectDenseHot vertices, hot_part non-null): a round
+    // whose gain is at least dense_gain (0: never) counts each block's decrements of hot
+    // vertices per hot position in LDS and stores them as the block's row of hot_part (grid
+    // rows of hot_n[0] counts); the next argmax subtracts the column sums from the hot
+    // counters.  hpos[v] is v's position in hot_ids, -1 for a cold vertex.
+    const int32_t* hpos;
+    int32_t* hot_part;
+    int32_t dense_gain;
+    int32_t pad2;
 };
 constexpr int kSelectHotBuckets = 4096;   // entries of SelInst::cnt_hist
 constexpr int kSelectHotPerBlock = 4096;  // hot vertices one block of the launch keeps at most
+constexpr int kSelectDenseHot = 16384;    // hot set of dense rounds at most (LDS counts)
+constexpr int kSelectDenseShare = 2048;   // ... and hot vertices per block at most
 constexpr int kMaxCoopGrid = 1024;   // blocks of a cooperative selection launch at most
 // Arrival counters of a hierarchical grid barrier (zeroed before each launch): block b
 // arrives on sub[b % 16]; the last arrival of a group bumps top; all wait for top.

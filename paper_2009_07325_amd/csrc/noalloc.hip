@@ -94,6 +94,7 @@ int64_t carve(unsigned char* base, const imm_pool* p, int64_t count, int32_t k_t
     w->hot_n = c.take<uint32_t>(2);
     w->hot_ids = c.take<int32_t>(hot_max);
     w->hot_cap = hot_max;
+    w->hpos = c.take<int32_t>(n);          // (no dense rounds: no hot_part rows)
     L->d_inst = c.take<SelInst>(1);
     L->bar = c.take<GridBarrier>(1);
     L->cap = 1;

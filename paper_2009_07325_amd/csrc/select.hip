@@ -438,14 +438,16 @@ __global__ __launch_bounds__(kCoopBlock) void k_hot_counts(const uint32_t* __res
 }
 
 // The hot threshold C (the smallest count below the last bucket with at most hot_max
-// counts above it) and the hot list {v : h[v] > C} (any order) with its bitmap (zeroed).
+// counts above it) and the hot list {v : h[v] > C} (any order) with its bitmap (zeroed) and
+// every vertex's position in it (hpos, -1 for the others).
 // Every block finds C from cnt_hist; hot_n[0] = list length, hot_n[1] = C (kHotOff: no
 // hot set).
 __global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restrict__ h, int64_t n,
                                                          const uint32_t* __restrict__ cnt_hist,
                                                          int32_t hot_max, uint32_t* __restrict__ hot_bits,
                                                          int32_t* __restrict__ hot_ids,
-                                                         uint32_t* __restrict__ hot_n) {
+                                                         uint32_t* __restrict__ hot_n,
+                                                         int32_t* __restrict__ hpos) {
     __shared__ int64_t pre[kCoopBlock + 1];
     __shared__ int64_t wsum[kCoopWaves];
     __shared__ int32_t s_thr;
@@ -487,7 +489,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restri
     }
     block_excl_scan_i64(mine, pre, wsum);
     const int64_t total = pre[kCoopBlock];
-    if (total == 0) return;
+    if (total == 0) {
+#pragma unroll
+        for (int j = 0; j < kHotListPer; ++j) {
+            const int64_t v = lo + (int64_t)j * kCoopBlock + tid;
+            if (v < n && hpos) hpos[v] = -1;
+        }
+        return;
+    }
     __shared__ uint32_t s_base;
     if (tid == 0) s_base = atomicAdd(hot_n, (uint32_t)total);
     __syncthreads();
@@ -496,22 +505,25 @@ __global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restri
     for (int j = 0; j < kHotListPer; ++j) {
         const int64_t v = lo + (int64_t)j * kCoopBlock + tid;
         if (c[j] > thr) {
+            if (hpos) hpos[v] = (int32_t)at;
             hot_ids[at++] = (int32_t)v;
             atomicOr(hot_bits + (v >> 5), 1u << (v & 31));
+        } else if (v < n && hpos) {
+            hpos[v] = -1;
         }
     }
 }
 
 hipError_t launch_hot_prepare(const uint32_t* hist, int32_t* h, int64_t n, int32_t hot_max,
                               uint32_t* cnt_hist, uint32_t* hot_bits, int32_t* hot_ids,
-                              uint32_t* hot_n, hipStream_t s) {
+                              uint32_t* hot_n, int32_t* hpos, hipStream_t s) {
     int64_t blocks = (n + kCoopBlock - 1) / kCoopBlock;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     k_hot_counts<<<(unsigned)blocks, kCoopBlock, 0, s>>>(hist, h, n, cnt_hist);
     const int64_t lblocks = (n + (int64_t)kCoopBlock * kHotListPer - 1) / ((int64_t)kCoopBlock * kHotListPer);
     k_hot_list<<<(unsigned)(lblocks > 0 ? lblocks : 1), kCoopBlock, 0, s>>>(h, n, cnt_hist, hot_max, hot_bits,
-                                                                          hot_ids, hot_n);
+                                                                          hot_ids, hot_n, hpos);
     return hipGetLastError();
 }
 
@@ -526,7 +538,8 @@ struct CoopLds {
     const int32_t* set_mem[kCoopBlock];
     int32_t set_inst[kCoopBlock];
     union {
-        DecCache dc;
+        DecCache dc;                    // decrement combining of ordinary rounds
+        int32_t dense[kSelectDenseHot]; // a dense round's decrements per hot position
     } u;
     unsigned char stopped[kMaxInst];    // estimation phase decided (failed)
     int64_t seg_pre[kMaxSegs + 1];      // single instance: its entries per segment
@@ -542,9 +555,12 @@ struct CoopLds {
 // members (consecutive lanes on consecutive members of a set, four per lane in flight),
 // each member found by a binary search over the prefix.  Skips each instance's chosen
 // vertex when skip_chosen, and, in batches of more than 4 x kCoopBlock members, vertices
-// outside the hot set when hot_bits is set.  All threads of the block.
+// outside the hot set when hot_bits is set.  With hpos set (a dense round of a single
+// instance) only hot vertices are decremented, each in the LDS count of its hot position.
+// All threads of the block.
 __device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t len, const int32_t* mem, int li,
-                          bool skip_chosen, const uint32_t* hot_bits) {
+                          bool skip_chosen, const uint32_t* hot_bits,
+                          const int32_t* hpos = nullptr) {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     block_excl_scan_i64(len, S.set_pre, S.wsum);
     S.set_mem[tid] = mem;
@@ -566,6 +582,15 @@ __device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t 
                 v[u] = global(S.set_mem[lo])[q - S.set_pre[lo]];
                 vi[u] = S.set_inst[lo];
             }
+        }
+        if (hpos) {
+            int32_t p[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] = vi[u] >= 0 ? global(hpos)[v[u]] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (p[u] >= 0 && v[u] != S.chosen[0]) atomicAdd(&S.u.dense[p[u]], 1);
+            continue;
         }
         if (hot_bits && total > 4 * kCoopBlock) {
             // cold counters are never read in hot mode (and the recount resets them), so a
@@ -663,6 +688,38 @@ __device__ __forceinline__ void reduce_block_keys(CoopLds& S, GridBarrier* bar) 
     __syncthreads();
 }
 
+// Column sums of hot_part over this block's hot positions [lo, lo + S.hot_cnt): acc[i] =
+// sum over the grid's rows of the count at position lo + i (rows of `total` counts).  Eight
+// loads per thread in flight.  All threads of the block.
+__device__ __noinline__ void dense_column_sums(CoopLds& S, const SelInst& I, int32_t* acc,
+                                               int32_t total, int32_t lo) {
+    const int tid = threadIdx.x;
+    const uint32_t cnt = (uint32_t)S.hot_cnt;
+    for (uint32_t i = tid; i < cnt; i += kCoopBlock) acc[i] = 0;
+    __syncthreads();
+    const uint32_t all = cnt * gridDim.x;
+    const IMM_GLOBAL int32_t* part = global(I.hot_part);
+    for (uint32_t q0 = 0; q0 < all; q0 += 8 * kCoopBlock) {
+        int32_t x[8];
+        uint32_t col[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t q = q0 + u * kCoopBlock + tid;
+            x[u] = 0;
+            col[u] = 0;
+            if (q < all) {
+                const uint32_t row = q / cnt;
+                col[u] = q - row * cnt;
+                x[u] = ld_co(part + (int64_t)row * total + lo + col[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (x[u] != 0) atomicAdd(&acc[col[u]], x[u]);
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __restrict__ inst,
                                                             int32_t ninst, int32_t maxk,
                                                             GridBarrier* bar) {
@@ -679,6 +736,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     // ---- hot set (single instance with hot_max > 0), prepared by k_hot_counts and
     // k_hot_list: this block's share of the list is kept in LDS for all rounds ----
     int32_t thr = kHotOff;
+    int32_t hot_total = 0, hot_lo = 0;          // hot list length; this block's first position
+    bool dense_ok = false;                       // dense rounds possible (uniform)
     if (solo && inst[0].hot_max > 0) {
         const SelInst& I = inst[0];
         thr = (int32_t)I.hot_n[1];
@@ -689,8 +748,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             const int64_t cnt = min(per, H - lo);
             for (int64_t i = tid; i < cnt; i += kCoopBlock) S.hot[i] = I.hot_ids[lo + i];
             if (tid == 0) S.hot_cnt = (int32_t)cnt;
+            hot_total = (int32_t)H;
+            hot_lo = (int32_t)lo;
+            dense_ok = I.hot_part && I.dense_gain > 0 && H <= kSelectDenseHot && per <= kSelectDenseShare;
         }
     }
+    bool prev_dense = false;                     // the previous round was dense (uniform)
+    static_assert(sizeof(S.set_pre) >= sizeof(int32_t) * kSelectDenseShare,
+                  "the column sums of a block's hot positions fit the batch prefix table");
     for (int i = threadIdx.x; i < kDecSlots; i += blockDim.x) {
         S.u.dc.key[i] = kDecEmpty;
         S.u.dc.cnt[i] = 0;
@@ -713,12 +778,30 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                         const int32_t tk = lane < parts ? ld_co(global(I.taken) + lane) : 0;
                         full = ballot(lane < parts && tk >= I.part_k);
                     }
+                    // after a dense round: its decrements of this block's hot positions are
+                    // the column sums of hot_part, accumulated in LDS (the batch prefix table
+                    // is free until the cover step)
+                    int32_t* acc = reinterpret_cast<int32_t*>(S.set_pre);
+                    if (prev_dense) dense_column_sums(S, I, acc, hot_total, hot_lo);
                     int32_t c[kHotPerThread], hv[kHotPerThread];
 #pragma unroll
                     for (int j = 0; j < kHotPerThread; ++j) {
                         const int i = tid + j * kCoopBlock;
                         hv[j] = i < S.hot_cnt ? S.hot[i] : -1;
                         c[j] = hv[j] >= 0 ? ld_co(global(I.h) + hv[j]) : -1;
+                    }
+                    if (prev_dense) {
+                        // the counters of this block's hot vertices take the dense round's
+                        // decrements (only this block writes them until the next barrier)
+#pragma unroll
+                        for (int j = 0; j < kHotPerThread; ++j) {
+                            const int i = tid + j * kCoopBlock;
+                            const int32_t d = hv[j] >= 0 ? acc[i] : 0;
+                            if (d != 0) {
+                                c[j] -= d;
+                                st_co(global(I.h) + hv[j], c[j]);
+                            }
+                        }
                     }
 #pragma unroll
                     for (int j = 0; j < kHotPerThread; ++j) {
@@ -819,6 +902,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         if (!__syncthreads_or(live)) return;            // every instance finished or stopped
         if (!solo) block_excl_scan_i64(cnt, S.ent_pre, S.wsum);
         const int64_t nent = S.ent_pre[ninst];
+        // a dense round: a single instance in hot mode with a large gain (uniform: every block
+        // holds the same key)
+        const bool dense = dense_ok && thr != kHotOff && S.key != 0 &&
+                           (int64_t)(S.key >> 32) - 1 >= (int64_t)inst[0].dense_gain;
+        if (dense) {
+            for (int i = tid; i < hot_total; i += kCoopBlock) S.u.dense[i] = 0;
+            __syncthreads();
+        }
         // Block b takes entries [nent b / G, nent (b+1) / G) in batches of one per thread:
         // each thread tests and marks its entry's set, and the batch's newly covered sets
         // are decremented together.
@@ -874,10 +965,24 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 mine += (unsigned long long)__popcll(mx);
                 pending &= ~mx;
             }
-            dec_batch(S, inst, len, mem, li, true, hot_bits);
+            dec_batch(S, inst, len, mem, li, true, hot_bits, dense ? inst[0].hpos : nullptr);
         }
         if (mine && lane == 0) atomic_add_agent(global(inst[mine_inst].n_covered), mine);
-        dec_flush(S.u.dc, inst);
+        if (dense) {
+            // the block's counts become its row of hot_part (every position, so no row needs
+            // clearing), and the LDS table returns to its empty state
+            __syncthreads();
+            IMM_GLOBAL int32_t* row = global(inst[0].hot_part) + (int64_t)blockIdx.x * hot_total;
+            for (int i = tid; i < hot_total; i += kCoopBlock) st_co(row + i, S.u.dense[i]);
+            __syncthreads();
+            for (int i = tid; i < kDecSlots; i += kCoopBlock) {
+                S.u.dc.key[i] = kDecEmpty;
+                S.u.dc.cnt[i] = 0;
+            }
+        } else {
+            dec_flush(S.u.dc, inst);
+        }
+        prev_dense = dense;
         if (!grid_sync(bar, epoch)) return;
     }
 }

@@ -118,3 +118,54 @@ def test_hot_mode_multi_round_partition(imm_gpu, monkeypatch, T):
     off, ids, _ = oracle.mr_sets(g, oracle.IC, seed, rounds, count, ic_p=p)
     seeds_o, cov_o = oracle.greedy_partition(g.n, rounds, off, ids, k)
     assert np.array_equal(seeds, seeds_o) and cov == cov_o
+
+
+@pytest.mark.parametrize("dense", ["1", "300"])
+@pytest.mark.parametrize("T", [None, 64])
+def test_dense_rounds_match_oracle(imm_gpu, monkeypatch, dense, T):
+    """Dense rounds: each block counts its decrements of hot vertices per hot position in
+    LDS, stores the counts as its row of a grid-wide table, and the next argmax subtracts the
+    column sums from the hot counters.  Forced for every hot round (gain >= 1) or for the
+    rounds with a large gain only, with the default hot set (hot mode throughout) and a small
+    one (dense rounds, then the recount); against the oracle's greedy and the selection with
+    dense rounds off."""
+    if T is None:
+        monkeypatch.delenv("IMM_SELECT_HOT", raising=False)
+    else:
+        monkeypatch.setenv("IMM_SELECT_HOT", str(T))
+    g = graphs.rmat(16, 16 << 16, seed=93)
+    p = graphs.weighted_cascade(g)
+    seed, count, k = 0x5EED0404, 20_000, 30
+    gg = imm_gpu.Graph.from_arrays(g.n, g.in_off, g.in_src, ic_p=p)
+    pool = imm_gpu.Pool.create(gg, imm_gpu.IMM_IC, seed)
+    imm_gpu.imm_generate_rr(pool.handle, count)
+    ref = oracle.Pool(g, oracle.IC, seed, ic_p=p)
+    ref.extend(count)
+    gains = _gains(ref, k, 0, count)
+    assert (gains >= int(dense)).sum() >= 2           # some rounds are dense
+    monkeypatch.setenv("IMM_SELECT_DENSE", dense)
+    seeds, cov = imm_gpu.imm_select_seeds(pool.handle, 0, count, k)
+    seeds_o, cov_o = ref.greedy(k, 0, count)
+    assert np.array_equal(seeds, seeds_o) and cov == cov_o
+    monkeypatch.setenv("IMM_SELECT_DENSE", "0")
+    seeds_0, cov_0 = imm_gpu.imm_select_seeds(pool.handle, 0, count, k)
+    assert np.array_equal(seeds_0, seeds_o) and cov_0 == cov_o
+
+
+def test_dense_rounds_growing_prefixes(imm_gpu, monkeypatch):
+    """Dense rounds over longer prefixes of one pool (index segments), each against the
+    oracle."""
+    monkeypatch.setenv("IMM_SELECT_HOT", "128")
+    monkeypatch.setenv("IMM_SELECT_DENSE", "1")
+    g = graphs.rmat(12, 12 << 12, seed=91)
+    p = graphs.weighted_cascade(g)
+    seed = 0x5EED0301
+    gg = imm_gpu.Graph.from_arrays(g.n, g.in_off, g.in_src, ic_p=p)
+    pool = imm_gpu.Pool.create(gg, imm_gpu.IMM_IC, seed)
+    ref = oracle.Pool(g, oracle.IC, seed, ic_p=p)
+    for end in (500, 1000, 2600, 4000, 5200):
+        imm_gpu.imm_generate_rr(pool.handle, end)
+        ref.extend(end)
+        seeds, cov = imm_gpu.imm_select_seeds(pool.handle, 0, end, 25)
+        seeds_o, cov_o = ref.greedy(25, 0, end)
+        assert np.array_equal(seeds, seeds_o) and cov == cov_o, end
