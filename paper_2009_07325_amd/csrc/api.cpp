@@ -490,8 +490,8 @@ extern "C" imm_status imm_rr_histogram(const imm_pool* pc, int64_t first, int64_
 // selection
 // ------------------------------------------------------------------------------------
 int64_t SelectWs::bytes() const {
-    int64_t b = (hot_bits ? (n + 31) / 32 * 4 + kSelectHotBuckets * 4 + 8 + n * 4 : 0) + hot_cap * 4 +
-                part_cap * 4;
+    int64_t b = (hot_words ? (n + 31) / 32 * 8 + hot_list_blocks(n) * 4 + kSelectHotBuckets * 4 + 8 : 0) +
+                hot_cap * 4 + part_cap * 4;
     if (h) b += n * (4 + 4 + 8 + 4) + 8;
     for (const IndexSeg& x : seg) b += x.off ? (n + 1) * 8 + x.cap * 4 : 0;
     if (snap) b += n * 4;
@@ -521,11 +521,11 @@ void SelectWs::release() {
     hfree(host_seeds);
     hfree(host_keys);
     hfree(host_cov);
-    dfree(hot_bits);
+    dfree(hot_words);
+    dfree(hot_blk);
     dfree(cnt_hist);
     dfree(hot_n);
     dfree(hot_ids);
-    dfree(hpos);
     dfree(hot_part);
     cap_cov = cap_k = hot_cap = part_cap = 0;
 }
@@ -622,12 +622,12 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
     IMM_TRY(ensure_select(p, w, count, k));
     const int32_t hot_max = hot ? select_hot_max(n) : 0;
     if (hot_max > 0) {
-        if (!w->hot_bits) {
-            IMM_TRY(dalloc(&w->hot_bits, (n + 31) / 32));
+        if (!w->hot_words) {
+            IMM_TRY(dalloc(&w->hot_words, (n + 31) / 32));
+            IMM_TRY(dalloc(&w->hot_blk, hot_list_blocks(n)));
             IMM_TRY(dalloc(&w->cnt_hist, kSelectHotBuckets));
             IMM_TRY(dalloc(&w->hot_n, 2));
         }
-        if (!w->hpos) IMM_TRY(dalloc(&w->hpos, n));
         if (hot_max > w->hot_cap) {
             dfree(w->hot_ids);
             IMM_TRY(dalloc(&w->hot_ids, hot_max));
@@ -675,11 +675,10 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
     }
     HIP_TRY(launch_fill_u32(w->covered, count, 0u, s));
     if (hot_max > 0) {
-        HIP_TRY(launch_fill_u32(w->hot_bits, (n + 31) / 32, 0u, s));
         HIP_TRY(launch_fill_u32(w->cnt_hist, kSelectHotBuckets, 0u, s));
         HIP_TRY(launch_fill_u32(w->hot_n, 2, 0u, s));
-        HIP_TRY(launch_hot_prepare(hsrc, w->h, n, hot_max, w->cnt_hist, w->hot_bits, w->hot_ids,
-                                   w->hot_n, w->hpos, s));
+        HIP_TRY(launch_hot_prepare(hsrc, w->h, n, hot_max, w->cnt_hist, w->hot_blk, w->hot_words,
+                                   w->hot_ids, w->hot_n, s));
     }
     HIP_TRY(launch_fill_u64(w->keys, k, 0ull, s));
     HIP_TRY(launch_fill_u64(w->n_covered, 1, 0ull, s));
@@ -710,10 +709,9 @@ imm_status imm::select_prepare(imm_pool* p, SelectWs* w, int64_t first, int64_t 
     si.n_covered = w->n_covered;
     si.h0 = hsrc;
     si.hot_max = hot_max;
-    si.hot_bits = w->hot_bits;
+    si.hot_words = w->hot_words;
     si.hot_n = w->hot_n;
     si.hot_ids = w->hot_ids;
-    si.hpos = w->hpos;
     if (hot_max > 0 && hot_max <= kSelectDenseHot &&
         w->part_cap >= (int64_t)select_coop_grid() * hot_max) {
         si.hot_part = w->hot_part;

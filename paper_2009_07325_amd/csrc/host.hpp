@@ -244,12 +244,12 @@ struct SelectWs {
     unsigned long long* host_cov = nullptr;   // pinned
     int32_t k = 0;                            // of the prepared selection
     // hot set of single-instance selections (select.hip)
-    uint32_t* hot_bits = nullptr;             // n bits
+    unsigned long long* hot_words = nullptr;  // (n + 31) / 32: hot bitmap | hot position << 32
+    uint32_t* hot_blk = nullptr;              // hot_list_blocks(n) counts
     uint32_t* cnt_hist = nullptr;             // kSelectHotBuckets
     uint32_t* hot_n = nullptr;
     int32_t* hot_ids = nullptr;               // hot_cap
     int64_t hot_cap = 0;
-    int32_t* hpos = nullptr;                  // n: position in hot_ids, -1 for a cold vertex
     int32_t* hot_part = nullptr;              // part_cap: per-block decrement rows of dense rounds
     int64_t part_cap = 0;
 

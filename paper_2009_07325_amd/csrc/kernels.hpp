@@ -170,11 +170,13 @@ hipError_t launch_sub_u32(const uint32_t* a, const uint32_t* b, uint32_t* out, i
 hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStream_t s);
 // Hot set of a single-instance selection: h = hist (as launch_copy_hist), the histogram of
 // the counts into cnt_hist (kSelectHotBuckets, zeroed), then the threshold and the hot list
-// into hot_bits (n bits, zeroed), hot_ids (hot_max) and hot_n (2 words, zeroed), and every
-// vertex's position in hot_ids (-1: cold) into hpos (n).
+// in increasing vertex order into hot_ids (hot_max) and hot_n (2 words, zeroed), and per 32
+// vertices their hot bitmap and hot position into hot_words ((n + 31) / 32); blk_cnt holds
+// hot_list_blocks(n) counts.
 hipError_t launch_hot_prepare(const uint32_t* hist, int32_t* h, int64_t n, int32_t hot_max,
-                              uint32_t* cnt_hist, uint32_t* hot_bits, int32_t* hot_ids,
-                              uint32_t* hot_n, int32_t* hpos, hipStream_t s);
+                              uint32_t* cnt_hist, uint32_t* blk_cnt, unsigned long long* hot_words,
+                              int32_t* hot_ids, uint32_t* hot_n, hipStream_t s);
+int64_t hot_list_blocks(int64_t n);
 // All k rounds of greedy selection for one or more instances in one cooperative launch:
 // per round a segmented argmax over every instance's counters, a grid barrier, the cover
 // step of every instance, a grid barrier.
@@ -218,20 +220,20 @@ struct SelInst {
     const int64_t* seg_off[kMaxSegs];
     const uint32_t* seg_inv[kMaxSegs];
     // Single-instance launches: hot set of at most hot_max vertices (0: off), prepared by
-    // launch_hot_prepare (hot_n[0] vertices in hot_ids and hot_bits, hot_n[1] the
-    // threshold); h0 holds the initial counts (n).
+    // launch_hot_prepare (hot_n[0] vertices in hot_ids, in increasing order, hot_n[1] the
+    // threshold; hot_words: per 32 vertices their hot bitmap (low half) and the hot position
+    // of the first of them (high half)); h0 holds the initial counts (n).
     const uint32_t* h0;
     int32_t hot_max;
     int32_t pad1;
-    const uint32_t* hot_bits;
+    const unsigned long long* hot_words;
     const uint32_t* hot_n;
     const int32_t* hot_ids;
     // Dense rounds (hot set of at most kSelectDenseHot vertices, hot_part non-null): a round
     // whose gain is at least dense_gain (0: never) counts each block's decrements of hot
     // vertices per hot position in LDS and stores them as the block's row of hot_part (grid
     // rows of hot_n[0] counts); the next argmax subtracts the column sums from the hot
-    // counters.  hpos[v] is v's position in hot_ids, -1 for a cold vertex.
-    const int32_t* hpos;
+    // counters.
     int32_t* hot_part;
     int32_t dense_gain;
     int32_t pad2;

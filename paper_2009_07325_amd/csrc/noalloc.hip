@@ -89,12 +89,12 @@ int64_t carve(unsigned char* base, const imm_pool* p, int64_t count, int32_t k_t
     w->seg[0].inv = c.take<uint32_t>(members);
     w->seg[0].cap = members;
     const int32_t hot_max = select_hot_max(n);
-    w->hot_bits = c.take<uint32_t>((n + 31) / 32);
+    w->hot_words = c.take<unsigned long long>((n + 31) / 32);
+    w->hot_blk = c.take<uint32_t>(hot_list_blocks(n));
     w->cnt_hist = c.take<uint32_t>(kSelectHotBuckets);
     w->hot_n = c.take<uint32_t>(2);
     w->hot_ids = c.take<int32_t>(hot_max);
     w->hot_cap = hot_max;
-    w->hpos = c.take<int32_t>(n);          // (no dense rounds: no hot_part rows)
     L->d_inst = c.take<SelInst>(1);
     L->bar = c.take<GridBarrier>(1);
     L->cap = 1;

@@ -437,19 +437,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_hot_counts(const uint32_t* __res
         if (chist[i]) atomicAdd(cnt_hist + i, chist[i]);
 }
 
-// The hot threshold C (the smallest count below the last bucket with at most hot_max
-// counts above it) and the hot list {v : h[v] > C} (any order) with its bitmap (zeroed) and
-// every vertex's position in it (hpos, -1 for the others).
-// Every block finds C from cnt_hist; hot_n[0] = list length, hot_n[1] = C (kHotOff: no
-// hot set).
-__global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restrict__ h, int64_t n,
-                                                         const uint32_t* __restrict__ cnt_hist,
-                                                         int32_t hot_max, uint32_t* __restrict__ hot_bits,
-                                                         int32_t* __restrict__ hot_ids,
-                                                         uint32_t* __restrict__ hot_n,
-                                                         int32_t* __restrict__ hpos) {
-    __shared__ int64_t pre[kCoopBlock + 1];
-    __shared__ int64_t wsum[kCoopWaves];
+// The hot threshold C: the smallest count below the last bucket with at most hot_max counts
+// above it (kHotOff: none).  All threads of the block.
+__device__ int32_t hot_threshold(const uint32_t* __restrict__ cnt_hist, int32_t hot_max,
+                                 int64_t* pre, int64_t* wsum) {
     __shared__ int32_t s_thr;
     const int tid = threadIdx.x;
     // thread t holds buckets kHotBuckets - 1 - (4t + j), j = 0..3 (descending)
@@ -473,58 +464,98 @@ __global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restri
     __syncthreads();
     if (cand != kHotOff) atomicMin(&s_thr, cand);
     __syncthreads();
-    const int32_t thr = s_thr;
+    return s_thr;
+}
+
+// Hot vertices among the kHotListPer consecutive vertices v0, v0 + 1, ... (bit j: v0 + j).
+__device__ __forceinline__ uint32_t hot_mask(const int32_t* __restrict__ h, int64_t n, int64_t v0,
+                                             int32_t thr) {
+    static_assert(kHotListPer == 16, "four 16-byte loads per thread");
+    uint32_t m = 0;
+    if (v0 + kHotListPer <= n) {
+        const int4* p = reinterpret_cast<const int4*>(h + v0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 x = p[q];
+            m |= ((uint32_t)(x.x > thr) | (uint32_t)(x.y > thr) << 1 | (uint32_t)(x.z > thr) << 2 |
+                  (uint32_t)(x.w > thr) << 3) << (4 * q);
+        }
+    } else {
+        for (int j = 0; j < kHotListPer; ++j)
+            if (v0 + j < n && h[v0 + j] > thr) m |= 1u << j;
+    }
+    return m;
+}
+
+// The threshold C (hot_n[1], by block 0), each block's number of hot vertices {v : h[v] > C}
+// in its range of kCoopBlock x kHotListPer vertices (blk_cnt), and their total (hot_n[0],
+// zeroed before).
+__global__ __launch_bounds__(kCoopBlock) void k_hot_threshold(const int32_t* __restrict__ h, int64_t n,
+                                                              const uint32_t* __restrict__ cnt_hist,
+                                                              int32_t hot_max,
+                                                              uint32_t* __restrict__ blk_cnt,
+                                                              uint32_t* __restrict__ hot_n) {
+    __shared__ int64_t pre[kCoopBlock + 1];
+    __shared__ int64_t wsum[kCoopWaves];
+    const int tid = threadIdx.x;
+    const int32_t thr = hot_threshold(cnt_hist, hot_max, pre, wsum);
     if (blockIdx.x == 0 && tid == 0) hot_n[1] = (uint32_t)thr;
     if (thr == kHotOff) return;
-    // the block's contiguous range of vertices, kHotListPer per thread: count its hot
-    // vertices, reserve their places with one atomic, then write them
-    const int64_t lo = (int64_t)blockIdx.x * kCoopBlock * kHotListPer;
-    int32_t c[kHotListPer];
-    int32_t mine = 0;
-#pragma unroll
-    for (int j = 0; j < kHotListPer; ++j) {
-        const int64_t v = lo + (int64_t)j * kCoopBlock + tid;
-        c[j] = v < n ? h[v] : -1;
-        mine += c[j] > thr;
-    }
-    block_excl_scan_i64(mine, pre, wsum);
-    const int64_t total = pre[kCoopBlock];
-    if (total == 0) {
-#pragma unroll
-        for (int j = 0; j < kHotListPer; ++j) {
-            const int64_t v = lo + (int64_t)j * kCoopBlock + tid;
-            if (v < n && hpos) hpos[v] = -1;
-        }
-        return;
-    }
-    __shared__ uint32_t s_base;
-    if (tid == 0) s_base = atomicAdd(hot_n, (uint32_t)total);
-    __syncthreads();
-    uint32_t at = s_base + (uint32_t)pre[tid];
-#pragma unroll
-    for (int j = 0; j < kHotListPer; ++j) {
-        const int64_t v = lo + (int64_t)j * kCoopBlock + tid;
-        if (c[j] > thr) {
-            if (hpos) hpos[v] = (int32_t)at;
-            hot_ids[at++] = (int32_t)v;
-            atomicOr(hot_bits + (v >> 5), 1u << (v & 31));
-        } else if (v < n && hpos) {
-            hpos[v] = -1;
-        }
+    const int64_t v0 = (int64_t)blockIdx.x * kCoopBlock * kHotListPer + (int64_t)tid * kHotListPer;
+    block_excl_scan_i64(__popc(hot_mask(h, n, v0, thr)), pre, wsum);
+    if (tid == 0) {
+        blk_cnt[blockIdx.x] = (uint32_t)pre[kCoopBlock];
+        if (pre[kCoopBlock]) atomicAdd(hot_n, (uint32_t)pre[kCoopBlock]);
     }
 }
 
+// The hot list in increasing vertex order (hot_ids) and, per 32 vertices, one word whose low
+// half is their hot bitmap and whose high half the number of hot vertices before them
+// (hot_words): the hot position of v is then high + popcount(low & (2^(v mod 32) - 1)).
+__global__ __launch_bounds__(kCoopBlock) void k_hot_list(const int32_t* __restrict__ h, int64_t n,
+                                                         const uint32_t* __restrict__ hot_n,
+                                                         const uint32_t* __restrict__ blk_cnt,
+                                                         int32_t* __restrict__ hot_ids,
+                                                         unsigned long long* __restrict__ hot_words) {
+    __shared__ int64_t pre[kCoopBlock + 1];
+    __shared__ int64_t wsum[kCoopWaves];
+    const int tid = threadIdx.x;
+    const int32_t thr = (int32_t)hot_n[1];
+    if (thr == kHotOff) return;
+    // hot vertices of the blocks before this one
+    int64_t before = 0;
+    for (uint32_t b = tid; b < blockIdx.x; b += kCoopBlock) before += blk_cnt[b];
+    block_excl_scan_i64(before, pre, wsum);
+    const int64_t base = pre[kCoopBlock];
+    const int64_t v0 = (int64_t)blockIdx.x * kCoopBlock * kHotListPer + (int64_t)tid * kHotListPer;
+    const uint32_t m = hot_mask(h, n, v0, thr);
+    block_excl_scan_i64(__popc(m), pre, wsum);
+    const int64_t first = base + pre[tid];       // hot position of this thread's first one
+    uint32_t at = (uint32_t)first;
+    for (uint32_t r = m; r != 0; r &= r - 1) hot_ids[at++] = (int32_t)(v0 + __ffs(r) - 1);
+    // two threads per word: the even one writes it
+    const uint32_t hi = (uint32_t)__shfl_xor((int)m, 1);
+    const int64_t w = v0 / 32;
+    if ((tid & 1) == 0 && w < (n + 31) / 32)
+        hot_words[w] = ((unsigned long long)(uint32_t)first << 32) | (unsigned long long)(m | (hi << 16));
+}
+
 hipError_t launch_hot_prepare(const uint32_t* hist, int32_t* h, int64_t n, int32_t hot_max,
-                              uint32_t* cnt_hist, uint32_t* hot_bits, int32_t* hot_ids,
-                              uint32_t* hot_n, int32_t* hpos, hipStream_t s) {
+                              uint32_t* cnt_hist, uint32_t* blk_cnt, unsigned long long* hot_words,
+                              int32_t* hot_ids, uint32_t* hot_n, hipStream_t s) {
     int64_t blocks = (n + kCoopBlock - 1) / kCoopBlock;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     k_hot_counts<<<(unsigned)blocks, kCoopBlock, 0, s>>>(hist, h, n, cnt_hist);
-    const int64_t lblocks = (n + (int64_t)kCoopBlock * kHotListPer - 1) / ((int64_t)kCoopBlock * kHotListPer);
-    k_hot_list<<<(unsigned)(lblocks > 0 ? lblocks : 1), kCoopBlock, 0, s>>>(h, n, cnt_hist, hot_max, hot_bits,
-                                                                          hot_ids, hot_n, hpos);
+    const int64_t lblocks = hot_list_blocks(n);
+    k_hot_threshold<<<(unsigned)lblocks, kCoopBlock, 0, s>>>(h, n, cnt_hist, hot_max, blk_cnt, hot_n);
+    k_hot_list<<<(unsigned)lblocks, kCoopBlock, 0, s>>>(h, n, hot_n, blk_cnt, hot_ids, hot_words);
     return hipGetLastError();
+}
+
+int64_t hot_list_blocks(int64_t n) {
+    const int64_t per = (int64_t)kCoopBlock * kHotListPer;
+    return n > 0 ? (n + per - 1) / per : 1;
 }
 
 struct CoopLds {
@@ -548,6 +579,7 @@ struct CoopLds {
     int32_t thr;
     int32_t hot_cnt;                    // this block's share of the hot list ...
     int32_t hot[kSelectHotPerBlock];    // ... kept for all rounds
+    int32_t csum[kCoopBlock];           // column sums of a dense round, per wave
 };
 
 // Decrements the counters of the members of every thread's set (len members at mem, of
@@ -555,12 +587,12 @@ struct CoopLds {
 // members (consecutive lanes on consecutive members of a set, four per lane in flight),
 // each member found by a binary search over the prefix.  Skips each instance's chosen
 // vertex when skip_chosen, and, in batches of more than 4 x kCoopBlock members, vertices
-// outside the hot set when hot_bits is set.  With hpos set (a dense round of a single
-// instance) only hot vertices are decremented, each in the LDS count of its hot position.
-// All threads of the block.
+// outside the hot set when hot_words is set.  In a dense round (a single instance) only hot
+// vertices are decremented, each in the LDS count of its hot position.  All threads of the
+// block.
 __device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t len, const int32_t* mem, int li,
-                          bool skip_chosen, const uint32_t* hot_bits,
-                          const int32_t* hpos = nullptr) {
+                          bool skip_chosen, const unsigned long long* hot_words,
+                          bool dense = false) {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     block_excl_scan_i64(len, S.set_pre, S.wsum);
     S.set_mem[tid] = mem;
@@ -572,6 +604,7 @@ __device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t q = q0 + u * kWave + lane;
+            v[u] = 0;
             vi[u] = -1;
             if (q < total) {
                 int lo = 0, hi = kCoopBlock;       // set_pre[lo] <= q < set_pre[lo + 1]
@@ -583,21 +616,24 @@ __device__ __noinline__ void dec_batch(CoopLds& S, const SelInst* inst, int64_t 
                 vi[u] = S.set_inst[lo];
             }
         }
-        if (hpos) {
-            int32_t p[4];
+        if (dense) {
+            unsigned long long hw[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) p[u] = vi[u] >= 0 ? global(hpos)[v[u]] : -1;
+            for (int u = 0; u < 4; ++u) hw[u] = vi[u] >= 0 ? global(hot_words)[v[u] >> 5] : 0ull;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (p[u] >= 0 && v[u] != S.chosen[0]) atomicAdd(&S.u.dense[p[u]], 1);
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t b = (uint32_t)v[u] & 31u, lo = (uint32_t)hw[u];
+                if (((lo >> b) & 1u) && v[u] != S.chosen[0])
+                    atomicAdd(&S.u.dense[(uint32_t)(hw[u] >> 32) + __popc(lo & ((1u << b) - 1u))], 1);
+            }
             continue;
         }
-        if (hot_bits && total > 4 * kCoopBlock) {
+        if (hot_words && total > 4 * kCoopBlock) {
             // cold counters are never read in hot mode (and the recount resets them), so a
             // small batch skips the bitmap test and its dependent load
             uint32_t w[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] = vi[u] >= 0 ? global(hot_bits)[v[u] >> 5] : 0u;
+            for (int u = 0; u < 4; ++u) w[u] = vi[u] >= 0 ? (uint32_t)global(hot_words)[v[u] >> 5] : 0u;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (!((w[u] >> (v[u] & 31)) & 1u)) vi[u] = -1;
@@ -689,35 +725,40 @@ __device__ __forceinline__ void reduce_block_keys(CoopLds& S, GridBarrier* bar) 
 }
 
 // Column sums of hot_part over this block's hot positions [lo, lo + S.hot_cnt): acc[i] =
-// sum over the grid's rows of the count at position lo + i (rows of `total` counts).  Eight
-// loads per thread in flight.  All threads of the block.
+// sum over the grid's rows of the count at position lo + i (rows of `total` counts).  A wave
+// takes 64 consecutive columns of every 16th row (8 loads per lane in flight); the 16 waves'
+// sums are added in LDS.  All threads of the block.
 __device__ __noinline__ void dense_column_sums(CoopLds& S, const SelInst& I, int32_t* acc,
                                                int32_t total, int32_t lo) {
-    const int tid = threadIdx.x;
-    const uint32_t cnt = (uint32_t)S.hot_cnt;
-    for (uint32_t i = tid; i < cnt; i += kCoopBlock) acc[i] = 0;
-    __syncthreads();
-    const uint32_t all = cnt * gridDim.x;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const int32_t cnt = S.hot_cnt, rows = (int32_t)gridDim.x;
     const IMM_GLOBAL int32_t* part = global(I.hot_part);
-    for (uint32_t q0 = 0; q0 < all; q0 += 8 * kCoopBlock) {
-        int32_t x[8];
-        uint32_t col[8];
+    for (int32_t c0 = 0; c0 < cnt; c0 += kWave) {
+        const int32_t col = c0 + lane;
+        int32_t sum = 0;
+        if (col < cnt) {
+            const IMM_GLOBAL int32_t* p = part + lo + col;
+            const int64_t step = (int64_t)kCoopWaves * total;
+            for (int32_t r0 = wid; r0 < rows; r0 += kCoopWaves * 8) {
+                int32_t x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t q = q0 + u * kCoopBlock + tid;
-            x[u] = 0;
-            col[u] = 0;
-            if (q < all) {
-                const uint32_t row = q / cnt;
-                col[u] = q - row * cnt;
-                x[u] = ld_co(part + (int64_t)row * total + lo + col[u]);
+                for (int j = 0; j < 8; ++j) {
+                    const int32_t r = r0 + j * kCoopWaves;
+                    x[j] = r < rows ? ld_co(p + (int64_t)r0 * total + j * step) : 0;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) sum += x[j];
             }
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (x[u] != 0) atomicAdd(&acc[col[u]], x[u]);
+        S.csum[wid * kWave + lane] = sum;
+        __syncthreads();
+        if (tid < kWave && c0 + tid < cnt) {
+            int32_t t = 0;
+            for (int w = 0; w < kCoopWaves; ++w) t += S.csum[w * kWave + tid];
+            acc[c0 + tid] = t;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __restrict__ inst,
@@ -915,7 +956,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
         // are decremented together.
         const int64_t e_lo = nent * (int64_t)blockIdx.x / gridDim.x;
         const int64_t e_hi = nent * ((int64_t)blockIdx.x + 1) / gridDim.x;
-        const uint32_t* hot_bits = thr != kHotOff ? inst[0].hot_bits : nullptr;
+        const unsigned long long* hot_words = thr != kHotOff ? inst[0].hot_words : nullptr;
         unsigned long long mine = 0;
         int mine_inst = -1;
         for (int64_t eb = e_lo; eb < e_hi; eb += kCoopBlock) {
@@ -965,7 +1006,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 mine += (unsigned long long)__popcll(mx);
                 pending &= ~mx;
             }
-            dec_batch(S, inst, len, mem, li, true, hot_bits, dense ? inst[0].hpos : nullptr);
+            dec_batch(S, inst, len, mem, li, true, hot_words, dense);
         }
         if (mine && lane == 0) atomic_add_agent(global(inst[mine_inst].n_covered), mine);
         if (dense) {
