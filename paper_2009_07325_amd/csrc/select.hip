@@ -579,7 +579,7 @@ struct CoopLds {
     int32_t thr;
     int32_t hot_cnt;                    // this block's share of the hot list ...
     int32_t hot[kSelectHotPerBlock];    // ... kept for all rounds
-    int32_t csum[kCoopBlock];           // column sums of a dense round, per wave
+    int32_t csum[2 * kCoopBlock];       // column sums of a dense round, per wave
 };
 
 // Decrements the counters of the members of every thread's set (len members at mem, of
@@ -724,38 +724,90 @@ __device__ __forceinline__ void reduce_block_keys(CoopLds& S, GridBarrier* bar) 
     __syncthreads();
 }
 
+// Rows of hot_part: 16-bit counts (a block's count for one hot vertex in one round is at most
+// its entries of the round, which a dense round keeps below 2^16), two per 32-bit word, rows
+// of dense_words(total) words.
+__device__ __forceinline__ int32_t dense_words(int32_t total) { return (total + 1) >> 1; }
+
+// The new seed's entries in every index segment of a single instance: lane j of wave 0 loads
+// segment j's range (all segments at once), into seg_beg / seg_pre and the entry count
+// ent_pre[1].  All threads of the block.
+__device__ __noinline__ void seg_ranges(CoopLds& S, const SelInst& I) {
+    const int lane = lane_id();
+    if (threadIdx.x < kWave) {
+        const int32_t u = S.chosen[0];
+        int64_t b = 0, c = 0;
+        if (lane < I.nseg) {
+            b = global(I.seg_off[lane])[u];
+            c = global(I.seg_off[lane])[u + 1] - b;
+        }
+        const int64_t incl = wave_incl_scan(c);
+        if (lane < I.nseg) {
+            S.seg_beg[lane] = b;
+            S.seg_pre[lane] = incl - c;
+        }
+        if (lane == I.nseg - 1) {
+            S.seg_pre[I.nseg] = incl;
+            S.ent_pre[1] = incl;
+        }
+    }
+    __syncthreads();
+}
+
+// This block's row of hot_part from its LDS counts (every position, so no row needs
+// clearing).  All threads of the block.
+__device__ __noinline__ void dense_store_row(CoopLds& S, const SelInst& I, int32_t total) {
+    const int32_t nw = dense_words(total);
+    IMM_GLOBAL uint32_t* row =
+        reinterpret_cast<IMM_GLOBAL uint32_t*>(global(I.hot_part)) + (int64_t)blockIdx.x * nw;
+    for (int i = threadIdx.x; i < nw; i += kCoopBlock) {
+        const uint32_t hi = 2 * i + 1 < total ? (uint32_t)S.u.dense[2 * i + 1] : 0u;
+        st_co(row + i, (uint32_t)S.u.dense[2 * i] | hi << 16);
+    }
+}
+
 // Column sums of hot_part over this block's hot positions [lo, lo + S.hot_cnt): acc[i] =
-// sum over the grid's rows of the count at position lo + i (rows of `total` counts).  A wave
-// takes 64 consecutive columns of every 16th row (8 loads per lane in flight); the 16 waves'
-// sums are added in LDS.  All threads of the block.
+// sum over the grid's rows of the count at position lo + i.  A wave takes 64 consecutive
+// words (128 positions) of every 16th row (8 loads per lane in flight); the 16 waves' sums
+// are added in LDS.  All threads of the block.
 __device__ __noinline__ void dense_column_sums(CoopLds& S, const SelInst& I, int32_t* acc,
                                                int32_t total, int32_t lo) {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    const int32_t cnt = S.hot_cnt, rows = (int32_t)gridDim.x;
-    const IMM_GLOBAL int32_t* part = global(I.hot_part);
-    for (int32_t c0 = 0; c0 < cnt; c0 += kWave) {
-        const int32_t col = c0 + lane;
-        int32_t sum = 0;
-        if (col < cnt) {
-            const IMM_GLOBAL int32_t* p = part + lo + col;
-            const int64_t step = (int64_t)kCoopWaves * total;
+    const int32_t cnt = S.hot_cnt, rows = (int32_t)gridDim.x, stride = dense_words(total);
+    const int32_t wlo = lo >> 1, whi = (lo + cnt + 1) >> 1;
+    const IMM_GLOBAL uint32_t* part = reinterpret_cast<const IMM_GLOBAL uint32_t*>(global(I.hot_part));
+    for (int32_t w0 = wlo; w0 < whi; w0 += kWave) {
+        const int32_t w = w0 + lane;
+        int32_t sum_lo = 0, sum_hi = 0;
+        if (w < whi) {
+            const IMM_GLOBAL uint32_t* p = part + w;
+            const int64_t step = (int64_t)kCoopWaves * stride;
             for (int32_t r0 = wid; r0 < rows; r0 += kCoopWaves * 8) {
-                int32_t x[8];
+                uint32_t x[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int32_t r = r0 + j * kCoopWaves;
-                    x[j] = r < rows ? ld_co(p + (int64_t)r0 * total + j * step) : 0;
+                    x[j] = r < rows ? ld_co(p + (int64_t)r0 * stride + j * step) : 0u;
                 }
 #pragma unroll
-                for (int j = 0; j < 8; ++j) sum += x[j];
+                for (int j = 0; j < 8; ++j) {
+                    sum_lo += (int32_t)(x[j] & 0xFFFFu);
+                    sum_hi += (int32_t)(x[j] >> 16);
+                }
             }
         }
-        S.csum[wid * kWave + lane] = sum;
+        S.csum[wid * kWave + lane] = sum_lo;
+        S.csum[kCoopBlock + wid * kWave + lane] = sum_hi;
         __syncthreads();
-        if (tid < kWave && c0 + tid < cnt) {
-            int32_t t = 0;
-            for (int w = 0; w < kCoopWaves; ++w) t += S.csum[w * kWave + tid];
-            acc[c0 + tid] = t;
+        if (tid < kWave && w0 + tid < whi) {
+            int32_t a = 0, b = 0;
+            for (int v = 0; v < kCoopWaves; ++v) {
+                a += S.csum[v * kWave + tid];
+                b += S.csum[kCoopBlock + v * kWave + tid];
+            }
+            const int32_t c = 2 * (w0 + tid) - lo;       // column of the low half
+            if (c >= 0 && c < cnt) acc[c] = a;
+            if (c + 1 >= 0 && c + 1 < cnt) acc[c + 1] = b;
         }
         __syncthreads();
     }
@@ -911,16 +963,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
                 const int32_t u = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
                 S.chosen[tid] = u;
                 if (I.nseg > 1) {              // only in single-instance launches
-                    int64_t acc = 0;
-                    for (int j = 0; j < I.nseg; ++j) {
-                        const int64_t b = global(I.seg_off[j])[u];
-                        S.seg_beg[j] = b;
-                        S.seg_pre[j] = acc;
-                        acc += global(I.seg_off[j])[u + 1] - b;
-                    }
-                    S.seg_pre[I.nseg] = acc;
-                    S.ent_beg[tid] = 0;
-                    cnt = acc;
+                    S.ent_beg[tid] = 0;        // the segment table follows (wave 0)
                 } else {
                     const int64_t beg = global(I.inv_off)[u];
                     S.ent_beg[tid] = beg;
@@ -941,11 +984,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             S.ent_pre[1] = cnt;
         }
         if (!__syncthreads_or(live)) return;            // every instance finished or stopped
+        if (solo && inst[0].nseg > 1) seg_ranges(S, inst[0]);
         if (!solo) block_excl_scan_i64(cnt, S.ent_pre, S.wsum);
         const int64_t nent = S.ent_pre[ninst];
         // a dense round: a single instance in hot mode with a large gain (uniform: every block
         // holds the same key)
-        const bool dense = dense_ok && thr != kHotOff && S.key != 0 &&
+        const bool dense = dense_ok && thr != kHotOff && S.key != 0 && nent <= 65535ll * gridDim.x &&
                            (int64_t)(S.key >> 32) - 1 >= (int64_t)inst[0].dense_gain;
         if (dense) {
             for (int i = tid; i < hot_total; i += kCoopBlock) S.u.dense[i] = 0;
@@ -1013,8 +1057,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
             // the block's counts become its row of hot_part (every position, so no row needs
             // clearing), and the LDS table returns to its empty state
             __syncthreads();
-            IMM_GLOBAL int32_t* row = global(inst[0].hot_part) + (int64_t)blockIdx.x * hot_total;
-            for (int i = tid; i < hot_total; i += kCoopBlock) st_co(row + i, S.u.dense[i]);
+            dense_store_row(S, inst[0], hot_total);
             __syncthreads();
             for (int i = tid; i < kDecSlots; i += kCoopBlock) {
                 S.u.dc.key[i] = kDecEmpty;
