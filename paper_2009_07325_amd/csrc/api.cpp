@@ -491,7 +491,7 @@ extern "C" imm_status imm_rr_histogram(const imm_pool* pc, int64_t first, int64_
 // ------------------------------------------------------------------------------------
 int64_t SelectWs::bytes() const {
     int64_t b = (hot_words ? (n + 31) / 32 * 8 + hot_list_blocks(n) * 4 + kSelectHotBuckets * 4 + 8 : 0) +
-                hot_cap * 4 + part_cap * 4;
+                hot_cap * 4 + part_cap * 4 + pair_cap * 8 + (bcur ? kInvBuckets * 8 : 0);
     if (h) b += n * (4 + 4 + 8 + 4) + 8;
     for (const IndexSeg& x : seg) b += x.off ? (n + 1) * 8 + x.cap * 4 : 0;
     if (snap) b += n * 4;
@@ -522,12 +522,14 @@ void SelectWs::release() {
     hfree(host_keys);
     hfree(host_cov);
     dfree(hot_words);
+    dfree(bcur);
+    dfree(pairs);
     dfree(hot_blk);
     dfree(cnt_hist);
     dfree(hot_n);
     dfree(hot_ids);
     dfree(hot_part);
-    cap_cov = cap_k = hot_cap = part_cap = 0;
+    cap_cov = cap_k = hot_cap = part_cap = pair_cap = 0;
 }
 
 void SelectLaunch::release() {
@@ -589,9 +591,23 @@ static imm_status index_segment(imm_pool* p, SelectWs* w, const uint32_t* cnt, i
         x.cap = c;
     }
     HIP_TRY(launch_scan_u32(cnt, n, x.off, w->scan_tmp, s));
-    HIP_TRY(launch_fill_u32(w->cursor, n, 0u, s));
-    HIP_TRY(launch_inv_scatter(p->rr_start, p->rr_len, p->ids, set_lo, set_n, rel0, x.off, w->cursor,
-                               x.inv, s));
+    // bucketed build (IMM_INV_BUCKETED=0 selects the per-entry atomic scatter)
+    const char* e = getenv("IMM_INV_BUCKETED");
+    if ((!e || atoi(e) != 0) && inv_bucket_shift(n) != 0 && !no_alloc_active()) {
+        if (!w->bcur) IMM_TRY(dalloc(&w->bcur, kInvBuckets));
+        if (members > w->pair_cap) {
+            dfree(w->pairs);
+            const int64_t c = members + members / 4 + 1024;
+            IMM_TRY(dalloc(&w->pairs, c));
+            w->pair_cap = c;
+        }
+        HIP_TRY(launch_inv_bucketed(p->rr_start, p->rr_len, p->ids, set_lo, set_n, rel0, x.off, n, w->bcur,
+                                    w->pairs, w->pair_cap, x.inv, s));
+    } else {
+        HIP_TRY(launch_fill_u32(w->cursor, n, 0u, s));
+        HIP_TRY(launch_inv_scatter(p->rr_start, p->rr_len, p->ids, set_lo, set_n, rel0, x.off, w->cursor,
+                                   x.inv, s));
+    }
     ++w->nseg;
     return IMM_OK;
 }

@@ -244,6 +244,9 @@ struct SelectWs {
     unsigned long long* host_cov = nullptr;   // pinned
     int32_t k = 0;                            // of the prepared selection
     // hot set of single-instance selections (select.hip)
+    unsigned long long* bcur = nullptr;       // kInvBuckets: bucketed index build cursors
+    uint2* pairs = nullptr;                   // pair_cap: (entry, vertex) of the bucketed build
+    int64_t pair_cap = 0;
     unsigned long long* hot_words = nullptr;  // (n + 31) / 32: hot bitmap | hot position << 32
     uint32_t* hot_blk = nullptr;              // hot_list_blocks(n) counts
     uint32_t* cnt_hist = nullptr;             // kSelectHotBuckets

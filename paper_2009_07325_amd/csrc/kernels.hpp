@@ -165,6 +165,15 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, const int32_t* ids,
                               int64_t first, int64_t count, uint32_t rel0, const int64_t* inv_off,
                               uint32_t* cursor, uint32_t* inv, hipStream_t s);
+// The same index without per-entry device atomics: entries grouped by buckets of vertices,
+// then placed per bucket (bcur: kInvBuckets cursors, pairs: one per entry).  Applies when
+// inv_bucket_shift(n) != 0.
+constexpr int kInvBuckets = 4096;  // vertex buckets of the bucketed index build at most
+int32_t inv_bucket_shift(int64_t n);
+hipError_t launch_inv_bucketed(const int64_t* rr_start, const int32_t* rr_len, const int32_t* ids,
+                               int64_t first, int64_t count, uint32_t rel0, const int64_t* inv_off,
+                               int64_t n, unsigned long long* bcur, uint2* pairs, int64_t pair_cap,
+                               uint32_t* inv, hipStream_t s);
 // out[v] = a[v] - b[v]
 hipError_t launch_sub_u32(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_copy_hist(const uint32_t* hist, int32_t* h, int32_t n, hipStream_t s);

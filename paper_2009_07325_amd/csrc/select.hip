@@ -196,6 +196,151 @@ hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, co
     return hipGetLastError();
 }
 
+// ---- inverted index by vertex buckets (no per-entry device atomics) -----------------
+// Vertices are grouped in buckets of 2^shift consecutive ids, at most kInvBuckets of them.
+// Pass 1 (one block per 256 sets): each block counts its members per bucket in LDS, takes
+// one range per bucket from the bucket's cursor (a device atomic per block and bucket), and
+// writes (entry, vertex) pairs there; a bucket's pairs then fill exactly the index range of
+// its vertices.  Pass 2 (one block per bucket): the bucket's vertices' next places are kept
+// in LDS, so each pair goes to its vertex's list with an LDS atomic.
+constexpr int kInvSetBlock = 256;
+constexpr int kInvPlaceBlock = 512;
+constexpr int kInvMaxShift = 13;
+
+__global__ void k_inv_bucket_init(const int64_t* __restrict__ off, int64_t n, int32_t shift, int32_t nb,
+                                  unsigned long long* __restrict__ bcur) {
+    const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) bcur[b] = (unsigned long long)off[min((int64_t)b << shift, n)];
+}
+
+__global__ __launch_bounds__(kInvSetBlock) void k_inv_bucket(const int64_t* __restrict__ rr_start,
+                                                             const int32_t* __restrict__ rr_len,
+                                                             const int32_t* __restrict__ ids,
+                                                             int64_t first, int64_t count, uint32_t rel0,
+                                                             int32_t shift, int32_t nb,
+                                                             unsigned long long* __restrict__ bcur,
+                                                             uint2* __restrict__ pairs, int64_t pair_cap) {
+    extern __shared__ unsigned char inv_lds[];
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(inv_lds);                        // nb
+    unsigned long long* base = reinterpret_cast<unsigned long long*>(cnt + ((nb + 1) & ~1));  // nb
+    __shared__ int64_t pre[kInvSetBlock + 1];
+    __shared__ int64_t sst[kInvSetBlock];
+    __shared__ int64_t sh[kScanBlock / kWave + 1];
+    static_assert(kInvSetBlock == kScanBlock, "block_excl_scan spans the block");
+    const int tid = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * kInvSetBlock;
+    const int64_t si = s0 + tid;
+    int64_t len = 0;
+    if (si < count) {
+        sst[tid] = rr_start[first + si];
+        len = rr_len[first + si];
+    }
+    for (int32_t b = tid; b < nb; b += kInvSetBlock) cnt[b] = 0;
+    int64_t total;
+    pre[tid] = block_excl_scan(len, sh, total);
+    if (tid == 0) pre[kInvSetBlock] = total;
+    __syncthreads();
+    // members q of the block's sets, flattened: set j with pre[j] <= q < pre[j + 1]
+    auto member = [&](int64_t q, int& j) {
+        int lo = 0, hi = kInvSetBlock;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= q) lo = mid; else hi = mid;
+        }
+        j = lo;
+        return ids[sst[lo] + (q - pre[lo])];
+    };
+    for (int64_t q0 = 0; q0 < total; q0 += 4 * kInvSetBlock) {
+        int32_t v[4];
+        int j;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = q0 + u * kInvSetBlock + tid;
+            v[u] = q < total ? member(q, j) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (v[u] >= 0) atomicAdd(&cnt[v[u] >> shift], 1u);
+    }
+    __syncthreads();
+    for (int32_t b = tid; b < nb; b += kInvSetBlock) {
+        const uint32_t c = cnt[b];
+        if (c) base[b] = atomic_add_agent(bcur + b, (unsigned long long)c);
+        cnt[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t q0 = 0; q0 < total; q0 += 4 * kInvSetBlock) {
+        int32_t v[4], js[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = q0 + u * kInvSetBlock + tid;
+            js[u] = 0;
+            v[u] = q < total ? member(q, js[u]) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (v[u] >= 0) {
+                const int32_t b = v[u] >> shift;
+                const unsigned long long at = base[b] + atomicAdd(&cnt[b], 1u);
+                if (at < (unsigned long long)pair_cap)
+                    pairs[at] = make_uint2(rel0 + (uint32_t)(s0 + js[u]), (uint32_t)v[u]);
+            }
+    }
+}
+
+__global__ __launch_bounds__(kInvPlaceBlock) void k_inv_place(const int64_t* __restrict__ off, int64_t n,
+                                                              int32_t shift, const uint2* __restrict__ pairs,
+                                                              uint32_t* __restrict__ inv) {
+    __shared__ uint32_t cur[1 << kInvMaxShift];
+    const int tid = threadIdx.x;
+    const int64_t v0 = (int64_t)blockIdx.x << shift;
+    const int64_t v1 = min(v0 + ((int64_t)1 << shift), n);
+    const int64_t r0 = off[v0], r1 = off[v1];
+    for (int64_t v = v0 + tid; v < v1; v += kInvPlaceBlock) cur[v - v0] = (uint32_t)(off[v] - r0);
+    __syncthreads();
+    for (int64_t e0 = r0; e0 < r1; e0 += 4 * kInvPlaceBlock) {
+        uint2 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + u * kInvPlaceBlock + tid;
+            p[u] = e < r1 ? pairs[e] : make_uint2(0u, 0xFFFFFFFFu);
+        }
+        // (the bounds tests only matter if the counts disagreed with the sets)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t vl = p[u].y - (uint32_t)v0;
+            if (vl < (uint32_t)(v1 - v0)) {
+                const int64_t at = r0 + atomicAdd(&cur[vl], 1u);
+                if (at < r1) inv[at] = p[u].x;
+            }
+        }
+    }
+}
+
+// Bucket shift for n vertices (0: the bucketed build does not apply).
+int32_t inv_bucket_shift(int64_t n) {
+    int32_t shift = 12;
+    while (shift <= kInvMaxShift && ((n + ((int64_t)1 << shift) - 1) >> shift) > kInvBuckets) ++shift;
+    return shift <= kInvMaxShift ? shift : 0;
+}
+
+hipError_t launch_inv_bucketed(const int64_t* rr_start, const int32_t* rr_len, const int32_t* ids,
+                               int64_t first, int64_t count, uint32_t rel0, const int64_t* inv_off,
+                               int64_t n, unsigned long long* bcur, uint2* pairs, int64_t pair_cap,
+                               uint32_t* inv, hipStream_t s) {
+    const int32_t shift = inv_bucket_shift(n);
+    if (shift == 0 || n < 1) return hipErrorInvalidValue;
+    if (count == 0) return hipSuccess;
+    const int32_t nb = (int32_t)((n + ((int64_t)1 << shift) - 1) >> shift);
+    k_inv_bucket_init<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(inv_off, n, shift, nb, bcur);
+    const size_t lds = sizeof(uint32_t) * (size_t)((nb + 1) & ~1) + sizeof(unsigned long long) * (size_t)nb;
+    const int64_t blocks = (count + kInvSetBlock - 1) / kInvSetBlock;
+    k_inv_bucket<<<(unsigned)blocks, kInvSetBlock, lds, s>>>(rr_start, rr_len, ids, first, count, rel0, shift,
+                                                            nb, bcur, pairs, pair_cap);
+    k_inv_place<<<(unsigned)nb, kInvPlaceBlock, 0, s>>>(inv_off, n, shift, pairs, inv);
+    return hipGetLastError();
+}
+
 __global__ void k_sub_u32(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
                           uint32_t* __restrict__ out, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
