@@ -197,7 +197,8 @@ hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, co
 }
 
 // ---- inverted index by vertex buckets (no per-entry device atomics) -----------------
-// Vertices are grouped in buckets of 2^shift consecutive ids, at most kInvBuckets of them.
+// Vertices are grouped in buckets of 2^shift consecutive ids (16 to 8192), at most
+// kInvBuckets of them.
 // Pass 1 (one block per 256 sets): each block counts its members per bucket in LDS, takes
 // one range per bucket from the bucket's cursor (a device atomic per block and bucket), and
 // writes (entry, vertex) pairs there; a bucket's pairs then fill exactly the index range of
@@ -317,11 +318,14 @@ __global__ __launch_bounds__(kInvPlaceBlock) void k_inv_place(const int64_t* __r
     }
 }
 
-// Bucket shift for n vertices (0: the bucketed build does not apply).
+// Bucket shift for n vertices (0: the bucketed build does not apply): the narrowest buckets
+// (at least 16 vertices) that make at most 1024 of them, so that small graphs still spread
+// the placement over many blocks, else at most kInvBuckets.
 int32_t inv_bucket_shift(int64_t n) {
-    int32_t shift = 12;
-    while (shift <= kInvMaxShift && ((n + ((int64_t)1 << shift) - 1) >> shift) > kInvBuckets) ++shift;
-    return shift <= kInvMaxShift ? shift : 0;
+    for (const int64_t most : {(int64_t)1024, (int64_t)kInvBuckets})
+        for (int32_t shift = 4; shift <= kInvMaxShift; ++shift)
+            if (((n + ((int64_t)1 << shift) - 1) >> shift) <= most) return shift;
+    return 0;
 }
 
 hipError_t launch_inv_bucketed(const int64_t* rr_start, const int32_t* rr_len, const int32_t* ids,
