@@ -476,6 +476,19 @@ bool tick(imm_server* S) {
     const double t0 = now_s();
     std::vector<SelInst> inst;
     std::vector<SelectWs*> ws;
+    // A launch of several instances reads every counter of every instance in each round; a
+    // single instance keeps exact counts for its most frequent vertices only (hot set).  On
+    // graphs large enough for a hot set, the tick's selections therefore run one launch
+    // each, with their hot sets; otherwise together in one launch.
+    size_t nsel = 0;
+    bool hot_all = true;
+    for (const Query& q : act) {
+        if (q.plan.reuses_last()) continue;
+        ++nsel;
+        if (select_hot_max(S->pools[q.model]->g->n) == 0) hot_all = false;
+    }
+    const bool each = nsel == 1 || hot_all;
+    imm_status st = IMM_OK;
     for (size_t i = 0; i < act.size();) {
         Query& q = act[i];
         if (q.plan.reuses_last()) {
@@ -483,26 +496,31 @@ bool tick(imm_server* S) {
             continue;
         }
         SelInst si{};
-        imm_status st = select_prepare(S->pools[q.model], &S->slots[q.slot], q.sel_first, q.sel_count,
-                                       q.k, S->stream, &si);
-        if (st != IMM_OK) {
+        const imm_status ps = select_prepare(S->pools[q.model], &S->slots[q.slot], q.sel_first, q.sel_count,
+                                             q.k, S->stream, &si, false, each);
+        if (ps != IMM_OK) {
             // this query's workspace did not fit: it alone fails, and its slot's memory is
             // given back for the others
             const std::string err = imm_last_error();
             S->slots[q.slot].release();
-            finish(S, q, st, err);
+            finish(S, q, ps, err);
             act.erase(act.begin() + (long)i);
             continue;
         }
         si.need = q.plan.need_cov();
         tr_sets += q.sel_count;
-        ws.push_back(&S->slots[q.slot]);
-        inst.push_back(si);
+        if (each) {
+            SelectWs* w = &S->slots[q.slot];
+            st = select_run(&S->launch, &w, &si, 1, S->stream);
+            if (st != IMM_OK) break;
+        } else {
+            ws.push_back(&S->slots[q.slot]);
+            inst.push_back(si);
+        }
         ++i;
     }
-    imm_status st = inst.empty() ? IMM_OK
-                                 : select_run(&S->launch, ws.data(), inst.data(), (int32_t)inst.size(),
-                                              S->stream);
+    if (st == IMM_OK && !inst.empty())
+        st = select_run(&S->launch, ws.data(), inst.data(), (int32_t)inst.size(), S->stream);
     const double dt = now_s() - t0;
     if (st != IMM_OK) {
         std::lock_guard<std::mutex> lk(S->mu);

@@ -41,9 +41,21 @@ def _alone(imm, gg, q):
 
 @pytest.mark.parametrize("max_active", [1, 4, 16])
 def test_served_results_equal_solo_solves(imm_gpu, served_graph, max_active):
+    _served_equal_solo(imm_gpu, served_graph, max_active, qseed=max_active)
+
+
+def test_served_hot_sets_one_launch_each(imm_gpu, served_graph, monkeypatch):
+    """With a hot set available (forced small here: 256 of 4096 vertices), the selections
+    of a tick run one launch each with their hot sets instead of one launch of several
+    instances; every answer still equals the solo solve."""
+    monkeypatch.setenv("IMM_SELECT_HOT", "256")
+    _served_equal_solo(imm_gpu, served_graph, 16, qseed=99)
+
+
+def _served_equal_solo(imm_gpu, served_graph, max_active, qseed):
     g, p, gg = served_graph
     imm = imm_gpu
-    qs = _queries(14, seed=max_active)
+    qs = _queries(14, seed=qseed)
     srv = imm.imm_server_create(gg.handle, SEED_IC, SEED_LT, 8 << 30, max_active)
     try:
         tickets = [imm.imm_server_submit(srv, q["k"], q["eps"], 1.0, q["model"]) for q in qs[:8]]
