@@ -234,6 +234,27 @@ def test_select_matches_oracle(imm_gpu, first, count, k):
     assert len(set(seeds_g.tolist())) == k
 
 
+@pytest.mark.parametrize("bucketed", ["0", "1"])
+def test_select_index_builds_match_oracle(imm_gpu, monkeypatch, bucketed):
+    """Both inverted-index builds: per-entry atomics (IMM_INV_BUCKETED=0, the form graphs
+    of more than 2^25 vertices take) and vertex buckets (the default), on growing prefixes
+    (index segments) of one pool, each selection against the oracle's greedy."""
+    monkeypatch.setenv("IMM_INV_BUCKETED", bucketed)
+    g = graphs.rmat(14, 12 << 14, seed=92)
+    ic_p = graphs.weighted_cascade(g)
+    gg = _gpu_graph(imm_gpu, g, ic_p=ic_p)
+    seed = 0x5EED0302
+    pool = imm_gpu.Pool.create(gg, imm_gpu.IMM_IC, seed)
+    ref = oracle.Pool(g, oracle.IC, seed, ic_p=ic_p)
+    for end in (3000, 7000, 12000):
+        imm_gpu.imm_generate_rr(pool.handle, end)
+        ref.extend(end)
+        seeds_g, cov_g = imm_gpu.imm_select_seeds(pool.handle, 0, end, 20)
+        seeds_o, cov_o = ref.greedy(20, 0, end)
+        assert np.array_equal(seeds_g, seeds_o), end
+        assert cov_g == cov_o, end
+
+
 def test_select_growing_prefixes_match_oracle(imm_gpu):
     """Selections over longer and longer prefixes of one pool read the inverted index as
     segments (one per batch of new sets, more segments than a solve makes); every
