@@ -2,7 +2,8 @@
 //
 // Per selection call over RR sets [first, first+count):
 //   1. h[v]   = number of those sets containing v (Occur, gIM Sec. III-B), as int32;
-//   2. an inverted index vertex -> RR indices (counting sort: scan of h, then scatter);
+//   2. an inverted index vertex -> RR indices (counting sort: scan of h, then the entries
+//      grouped by buckets of vertices and placed bucket by bucket);
 //   3. k rounds of
 //        argmax  : u = the vertex outside S with the largest h, smallest id among equals
 //                  (gIM Sec. III-H: a max reduction over Occur);
@@ -1220,8 +1221,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_select_coop(const SelInst* __res
     }
 }
 
-// One 1024-thread block per CU.  With this kernel's resources (about 92 KB of LDS and
-// 126 VGPRs per lane, i.e. 4 waves per SIMD) one block per CU is also the most a CU can
+// One 1024-thread block per CU.  With this kernel's resources (about 141 KB of LDS and
+// 128 VGPRs per lane, i.e. 4 waves per SIMD) one block per CU is also the most a CU can
 // hold, so the grid is exactly the device's capacity and every block is resident while
 // no other kernel occupies the CUs.
 int select_coop_grid() {
