@@ -200,12 +200,13 @@ hipError_t launch_inv_scatter(const int64_t* rr_start, const int32_t* rr_len, co
 // ---- inverted index by vertex buckets (no per-entry device atomics) -----------------
 // Vertices are grouped in buckets of 2^shift consecutive ids (16 to 8192), at most
 // kInvBuckets of them.
-// Pass 1 (one block per 256 sets): each block counts its members per bucket in LDS, takes
+// Pass 1 (one block of 256 threads per 128 sets): each block counts its members per bucket in LDS, takes
 // one range per bucket from the bucket's cursor (a device atomic per block and bucket), and
 // writes (entry, vertex) pairs there; a bucket's pairs then fill exactly the index range of
 // its vertices.  Pass 2 (one block per bucket): the bucket's vertices' next places are kept
 // in LDS, so each pair goes to its vertex's list with an LDS atomic.
 constexpr int kInvSetBlock = 256;
+constexpr int kInvSets = 128;                // sets per block of pass 1
 constexpr int kInvPlaceBlock = 512;
 constexpr int kInvMaxShift = 13;
 
@@ -230,10 +231,10 @@ __global__ __launch_bounds__(kInvSetBlock) void k_inv_bucket(const int64_t* __re
     __shared__ int64_t sh[kScanBlock / kWave + 1];
     static_assert(kInvSetBlock == kScanBlock, "block_excl_scan spans the block");
     const int tid = threadIdx.x;
-    const int64_t s0 = (int64_t)blockIdx.x * kInvSetBlock;
+    const int64_t s0 = (int64_t)blockIdx.x * kInvSets;
     const int64_t si = s0 + tid;
     int64_t len = 0;
-    if (si < count) {
+    if (tid < kInvSets && si < count) {
         sst[tid] = rr_start[first + si];
         len = rr_len[first + si];
     }
@@ -339,7 +340,7 @@ hipError_t launch_inv_bucketed(const int64_t* rr_start, const int32_t* rr_len, c
     const int32_t nb = (int32_t)((n + ((int64_t)1 << shift) - 1) >> shift);
     k_inv_bucket_init<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(inv_off, n, shift, nb, bcur);
     const size_t lds = sizeof(uint32_t) * (size_t)((nb + 1) & ~1) + sizeof(unsigned long long) * (size_t)nb;
-    const int64_t blocks = (count + kInvSetBlock - 1) / kInvSetBlock;
+    const int64_t blocks = (count + kInvSets - 1) / kInvSets;
     k_inv_bucket<<<(unsigned)blocks, kInvSetBlock, lds, s>>>(rr_start, rr_len, ids, first, count, rel0, shift,
                                                             nb, bcur, pairs, pair_cap);
     k_inv_place<<<(unsigned)nb, kInvPlaceBlock, 0, s>>>(inv_off, n, shift, pairs, inv);
